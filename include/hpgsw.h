@@ -1,0 +1,187 @@
+/*
+ * hpgsw.h -- batched Smith-Waterman (affine gaps) for RNA-seq read alignment
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the alignment task of the paper's stage E (Sec. 2,
+ * "Stage E: SWA + Splice Junctions", task iii): every read is aligned with
+ * the Smith-Waterman local alignment algorithm against each of its extended
+ * candidate alignment locations (windows), and the alignment, its score and
+ * its start position are returned; task iv keeps the alignments whose score
+ * reaches a threshold.  Windows come from the CAL seeker (Sec. 2, "Stage D:
+ * CAL Seeker"), extended on both sides (stage E, task i).
+ *
+ * Scoring model (the paper leaves it open; this library fixes Gotoh's affine
+ * gaps with signed integer scores):
+ *   E(i,j) = max(H(i,j-1) + gap_open, E(i,j-1) + gap_extend)   deletion (consumes window)
+ *   F(i,j) = max(H(i-1,j) + gap_open, F(i-1,j) + gap_extend)   insertion (consumes read)
+ *   H(i,j) = max(0, H(i-1,j-1) + s(q_i, r_j), E(i,j), F(i,j)),  H = 0 on row/column 0
+ * so a gap of k bases costs gap_open + (k-1)*gap_extend.  The best score S is
+ * the maximum of H.  End cell: among cells with H == S, the smallest window
+ * position, then the smallest read position.  Traceback from the end cell:
+ * diagonal before deletion before insertion, a gap opens as soon as opening
+ * reaches the value, and the path stops at the first H == 0.  All results are
+ * exact integers; the library never approximates.
+ *
+ * Conventions for every call:
+ *   - Returns sw_status (0 = SW_OK, < 0 = error) and never throws or aborts;
+ *     sw_last_error() holds a message for the last failing call on a context.
+ *   - Pointers named d_* are DEVICE pointers owned by the caller; the library
+ *     never frees them.  Other pointers are host pointers, read during the call.
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = the
+ *     default stream) and is asynchronous: outputs are valid once the stream
+ *     has synchronised.  Scratch that the library allocates belongs to the
+ *     context; calls on one context must not overlap (one context per host
+ *     thread and stream).
+ *   - Sequences are 2-bit packed: base p of a sequence buffer sits in 32-bit
+ *     word p >> 4, bits 2*(p & 15) .. 2*(p & 15)+1, codes A=0 C=1 G=2 T=3.  A
+ *     packed buffer of L bases holds ceil(L/16) words (sw_pack2b writes this).
+ *   - Window coordinates are 0-based and inclusive; ref_* coordinates are
+ *     relative to the window start, read_* coordinates to the query.  For a
+ *     window with strand 1 the query is the reverse complement of the read.
+ *
+ * Limits: read and window lengths up to 65,535; scores with
+ * 0 < match <= 127, -127 <= mismatch < match, -127 <= gap_open < 0 and
+ * gap_open <= gap_extend <= 0 (otherwise SW_E_INVALID).
+ */
+#ifndef HPGSW_H
+#define HPGSW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SW_OK = 0,
+    SW_E_INVALID = -1,  /* bad argument (NULL pointer, bad scoring, bad flags) */
+    SW_E_RANGE = -2,    /* a size is out of the supported range */
+    SW_E_NOMEM = -3,    /* device allocation of scratch failed */
+    SW_E_DEVICE = -4,   /* a HIP runtime call failed */
+    SW_E_NODEVICE = -5, /* no usable gfx950 device */
+    SW_E_STATE = -6     /* object used in the wrong state */
+} sw_status;
+
+typedef struct sw_ctx sw_ctx;
+
+/* Integer scoring scheme; e.g. {+5, -4, -10, -1}. */
+typedef struct {
+    int32_t match, mismatch, gap_open, gap_extend;
+} sw_scoring;
+
+/* One candidate window (an extended CAL) of one read: 12 bytes, packed.
+ * The window is reference bases [ref_begin, ref_begin + len), clipped to the
+ * reference.  strand 1: align the reverse complement of the read.  flags are
+ * carried for the caller and ignored by the library. */
+typedef struct {
+    uint32_t read_id;
+    uint32_t ref_begin;
+    uint16_t len;
+    uint8_t strand;
+    uint8_t flags;
+} sw_window;
+
+/* A batch: one packed reference, packed reads, and (read, window) pairs. */
+typedef struct {
+    const uint32_t *d_ref2b;      /* packed reference, ceil(ref_len/16) words */
+    uint64_t ref_len;             /* bases */
+    const uint32_t *d_reads2b;    /* packed reads, concatenated */
+    uint64_t reads_len;           /* bases in d_reads2b */
+    const uint64_t *d_read_off;   /* [n_reads] base offset of each read in d_reads2b */
+    const uint16_t *d_read_len;   /* [n_reads] read lengths */
+    uint32_t n_reads;
+    const sw_window *d_win;       /* [n_pairs] windows, any order */
+    uint32_t n_pairs;
+} sw_batch;
+
+/* Score result of one pair.  score -1 marks an invalid pair (read_id out of
+ * range); score 0 means no alignment (ends -1).  Ends are filled only with
+ * SW_WANT_ENDS, else -1. */
+typedef struct {
+    int32_t score, read_end, ref_end;
+} sw_hit;
+
+/* Full alignment of one pair (sw_batch_traceback). */
+typedef struct {
+    int32_t score, read_begin, read_end, ref_begin, ref_end;
+    uint32_t n_ops;   /* CIGAR ops written for this pair */
+    uint32_t status;  /* bit0: ops truncated to ops_stride; bit1: invalid pair */
+} sw_aln;
+
+#define SW_WANT_ENDS 1u
+
+/* CIGAR op codes, as in SAM/BAM; an op is (len << 4) | code. */
+#define SW_OP_M 0u
+#define SW_OP_I 1u
+#define SW_OP_D 2u
+#define SW_OP_N 3u
+#define SW_OP_S 4u
+
+/* Create a context on HIP device `hip_device` (must be gfx950).  *out receives
+ * the context; destroy it with sw_ctx_destroy.  SW_E_NODEVICE if the device
+ * does not exist or is not gfx950. */
+sw_status sw_ctx_create(int hip_device, sw_ctx **out);
+sw_status sw_ctx_destroy(sw_ctx *ctx);
+const char *sw_last_error(const sw_ctx *ctx);
+
+/* Encode step: pack n ASCII bases (d_ascii, bytes 'A','C','G','T') into
+ * d_out (ceil(n/16) 32-bit words, unused high bits zero).  Any other byte is
+ * encoded as A and counted into *d_bad (device uint32, may be NULL; it is
+ * incremented, not cleared).  The read and reference encoding of Sec. 2,
+ * stage A (reads are held with their sequence), in the 2-bit form the
+ * aligner reads. */
+sw_status sw_pack2b(sw_ctx *ctx, const uint8_t *d_ascii, uint64_t n, uint32_t *d_out,
+                    uint32_t *d_bad, void *stream);
+
+/* Best local alignment score of every (read, window) pair of `batch` (Sec. 2,
+ * stage E task iii).  d_hits[n_pairs] receives scores, and end coordinates if
+ * flags has SW_WANT_ENDS.  Pairs are bucketed by length and scheduled onto
+ * persistent kernels; results do not depend on pair order or bucketing. */
+sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *batch, const sw_scoring *sc,
+                         uint32_t flags, sw_hit *d_hits, void *stream);
+
+/* Best hit per read (Sec. 2, stage E task iv): for every read, the pair with
+ * the highest score among its windows (lowest pair index on ties) and that
+ * score.  Reads without windows get best_pair 0xFFFFFFFF and score -1.
+ * d_mapped (may be NULL) receives 1 where best_score >= t_map (a successful
+ * mapping), else 0. */
+sw_status sw_best_per_read(sw_ctx *ctx, const sw_batch *batch, const sw_hit *d_hits,
+                           int32_t t_map, uint32_t *d_best_pair, int32_t *d_best_score,
+                           uint8_t *d_mapped, void *stream);
+
+/* Full alignments with CIGAR for the pairs listed in d_pair_ids[n_sel]
+ * (Sec. 2, stage E task iii: the alignment and its start position, which the
+ * junction search of task iv reads).  d_aln[n_sel] receives coordinates;
+ * d_ops[n_sel * ops_stride] receives each pair's ops, soft clips included.
+ * A pair whose CIGAR needs more than ops_stride ops gets the first
+ * ops_stride ops and status bit0.  m + n + 2 ops always suffice. */
+sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *batch, const sw_scoring *sc,
+                             const uint32_t *d_pair_ids, uint32_t n_sel, sw_aln *d_aln,
+                             uint32_t *d_ops, uint32_t ops_stride, void *stream);
+
+/* Phase timing of sw_batch_score, from HIP events recorded on the call's
+ * stream.  bucket_ms covers the length bucketing; class_ms[c] the wavefront
+ * kernel of query-length class c (classes: m <= 16, 32, 64, 100, 128, 160,
+ * 256, 512, 1024, 2048, longer); score_ms their sum. */
+typedef struct {
+    float bucket_ms;
+    float score_ms;
+    float class_ms[16];
+} sw_timing;
+
+/* Turn event recording on (on != 0) or off for later sw_batch_score calls. */
+sw_status sw_timing_enable(sw_ctx *ctx, int on);
+
+/* Times of the last timed sw_batch_score call; waits for its events.
+ * SW_E_STATE if timing is off or no call was timed. */
+sw_status sw_timing_get(sw_ctx *ctx, sw_timing *out);
+
+/* Format ops as CIGAR text into buf (host memory); returns the length
+ * written, or -1 if cap is too small. */
+int sw_cigar_string(const uint32_t *ops, uint32_t n_ops, char *buf, uint32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPGSW_H */

@@ -1,0 +1,215 @@
+"""Python binding of libhpgsw (batched Smith-Waterman for RNA-seq reads on MI355X).
+
+Argument marshalling only: every step of the alignment path runs in the HIP
+kernels of ``libhpgsw.so``; PyTorch provides device memory and streams.  The
+functions mirror the C ABI in ``include/hpgsw.h`` one to one.  If the library
+is missing or no gfx950 device is present, the calls fail loudly; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhpgsw.so")
+
+SW_OK, SW_E_INVALID, SW_E_RANGE, SW_E_NOMEM, SW_E_DEVICE, SW_E_NODEVICE, SW_E_STATE = \
+    0, -1, -2, -3, -4, -5, -6
+SW_WANT_ENDS = 1
+OP_NAMES = "MIDNS"
+
+HIT_DTYPE = np.dtype([("score", "<i4"), ("read_end", "<i4"), ("ref_end", "<i4")])
+ALN_DTYPE = np.dtype([("score", "<i4"), ("read_begin", "<i4"), ("read_end", "<i4"),
+                      ("ref_begin", "<i4"), ("ref_end", "<i4"), ("n_ops", "<u4"),
+                      ("status", "<u4")])
+WINDOW_DTYPE = np.dtype([("read_id", "<u4"), ("ref_begin", "<u4"), ("len", "<u2"),
+                         ("strand", "u1"), ("flags", "u1")])
+
+
+class SwError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hpgsw status {status}: {msg}")
+        self.status = status
+
+
+class sw_scoring(ctypes.Structure):
+    _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32),
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
+
+
+class sw_timing(ctypes.Structure):
+    _fields_ = [("bucket_ms", ctypes.c_float), ("score_ms", ctypes.c_float),
+                ("class_ms", ctypes.c_float * 16)]
+
+
+class sw_batch(ctypes.Structure):
+    _fields_ = [("d_ref2b", ctypes.c_void_p), ("ref_len", ctypes.c_uint64),
+                ("d_reads2b", ctypes.c_void_p), ("reads_len", ctypes.c_uint64),
+                ("d_read_off", ctypes.c_void_p), ("d_read_len", ctypes.c_void_p),
+                ("n_reads", ctypes.c_uint32), ("d_win", ctypes.c_void_p),
+                ("n_pairs", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhpgsw.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1304_0681_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, U32, U64, I32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+        L.sw_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+        L.sw_ctx_destroy.argtypes = [P]
+        L.sw_last_error.argtypes = [P]
+        L.sw_last_error.restype = ctypes.c_char_p
+        L.sw_pack2b.argtypes = [P, P, U64, P, P, P]
+        L.sw_batch_score.argtypes = [P, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scoring), U32,
+                                     P, P]
+        L.sw_best_per_read.argtypes = [P, ctypes.POINTER(sw_batch), P, I32, P, P, P, P]
+        L.sw_batch_traceback.argtypes = [P, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scoring),
+                                         P, U32, P, P, U32, P]
+        L.sw_cigar_string.argtypes = [P, U32, ctypes.c_char_p, U32]
+        L.sw_timing_enable.argtypes = [P, ctypes.c_int]
+        L.sw_timing_get.argtypes = [P, ctypes.POINTER(sw_timing)]
+        for f in ("sw_ctx_create", "sw_ctx_destroy", "sw_pack2b", "sw_batch_score",
+                  "sw_best_per_read", "sw_batch_traceback", "sw_cigar_string",
+                  "sw_timing_enable", "sw_timing_get"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check(ctx, st):
+    if st != SW_OK:
+        raise SwError(st, lib().sw_last_error(ctx).decode())
+
+
+def sw_ctx_create(device: int = 0):
+    h = ctypes.c_void_p()
+    st = lib().sw_ctx_create(device, ctypes.byref(h))
+    if st != SW_OK:
+        raise SwError(st, lib().sw_last_error(None).decode())
+    return h
+
+
+def sw_ctx_destroy(ctx):
+    lib().sw_ctx_destroy(ctx)
+
+
+def sw_pack2b(ctx, d_ascii, n, d_out, d_bad=None, stream=None):
+    _check(ctx, lib().sw_pack2b(ctx, _ptr(d_ascii), int(n), _ptr(d_out), _ptr(d_bad),
+                                _stream_ptr(stream)))
+
+
+def sw_batch_score(ctx, batch, scoring, flags, d_hits, stream=None):
+    _check(ctx, lib().sw_batch_score(ctx, ctypes.byref(batch.c), ctypes.byref(_sc(scoring)),
+                                     int(flags), _ptr(d_hits), _stream_ptr(stream)))
+
+
+def sw_best_per_read(ctx, batch, d_hits, t_map, d_best_pair, d_best_score, d_mapped=None,
+                     stream=None):
+    _check(ctx, lib().sw_best_per_read(ctx, ctypes.byref(batch.c), _ptr(d_hits), int(t_map),
+                                       _ptr(d_best_pair), _ptr(d_best_score), _ptr(d_mapped),
+                                       _stream_ptr(stream)))
+
+
+def sw_batch_traceback(ctx, batch, scoring, d_pair_ids, n_sel, d_aln, d_ops, ops_stride,
+                       stream=None):
+    _check(ctx, lib().sw_batch_traceback(ctx, ctypes.byref(batch.c), ctypes.byref(_sc(scoring)),
+                                         _ptr(d_pair_ids), int(n_sel), _ptr(d_aln), _ptr(d_ops),
+                                         int(ops_stride), _stream_ptr(stream)))
+
+
+def sw_timing_enable(ctx, on=True):
+    _check(ctx, lib().sw_timing_enable(ctx, 1 if on else 0))
+
+
+def sw_timing_get(ctx) -> sw_timing:
+    t = sw_timing()
+    _check(ctx, lib().sw_timing_get(ctx, ctypes.byref(t)))
+    return t
+
+
+def sw_cigar_string(ops) -> str:
+    a = np.ascontiguousarray(ops, dtype=np.uint32)
+    buf = ctypes.create_string_buffer(16 * len(a) + 1)
+    n = lib().sw_cigar_string(a.ctypes.data_as(ctypes.c_void_p), len(a), buf, len(buf))
+    if n < 0:
+        raise SwError(SW_E_INVALID, "CIGAR buffer too small")
+    return buf.value.decode()
+
+
+def _sc(scoring) -> sw_scoring:
+    if isinstance(scoring, sw_scoring):
+        return scoring
+    return sw_scoring(*[int(x) for x in scoring])
+
+
+class DeviceBatch:
+    """A batch resident in device memory: packed reference, packed reads, windows.
+
+    Built from ASCII host arrays; the 2-bit encoding runs on the device through
+    sw_pack2b.  Keeps the torch tensors alive as long as the batch exists.
+    """
+
+    def __init__(self, ctx, ref_ascii, reads_ascii, read_off, read_len, windows, stream=None,
+                 ref2b=None):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.ctx = ctx
+        self.bad = torch.zeros(1, dtype=torch.int32, device=dev)
+        if ref2b is None:
+            self.ref_ascii = torch.from_numpy(np.ascontiguousarray(ref_ascii)).to(dev)
+            self.ref2b = torch.empty((len(ref_ascii) + 15) // 16, dtype=torch.int32, device=dev)
+            sw_pack2b(ctx, self.ref_ascii, len(ref_ascii), self.ref2b, self.bad, stream)
+            self.ref_len = len(ref_ascii)
+        else:
+            self.ref2b, self.ref_len = ref2b
+        self.reads_ascii = torch.from_numpy(np.ascontiguousarray(reads_ascii)).to(dev)
+        self.reads_len = len(reads_ascii)
+        self.reads2b = torch.empty(max((self.reads_len + 15) // 16, 1), dtype=torch.int32,
+                                   device=dev)
+        self.read_off = torch.from_numpy(np.ascontiguousarray(read_off, dtype=np.uint64)
+                                         .view(np.int64)).to(dev)
+        self.read_len = torch.from_numpy(np.ascontiguousarray(read_len, dtype=np.uint16)
+                                         .view(np.int16)).to(dev)
+        w = np.ascontiguousarray(windows).view(np.uint8)
+        self.win = torch.from_numpy(w.copy()).to(dev)
+        self.n_reads = len(read_len)
+        self.n_pairs = len(windows)
+        self.pack_reads(stream)
+        self.c = sw_batch(_ptr(self.ref2b), self.ref_len, _ptr(self.reads2b), self.reads_len,
+                          _ptr(self.read_off), _ptr(self.read_len), self.n_reads, _ptr(self.win),
+                          self.n_pairs)
+
+    def pack_reads(self, stream=None):
+        """Encode step for the reads (ASCII already in device memory)."""
+        sw_pack2b(self.ctx, self.reads_ascii, self.reads_len, self.reads2b, self.bad, stream)
+
+    @classmethod
+    def from_synth(cls, ctx, b, stream=None):
+        return cls(ctx, b.ref, b.reads, b.read_off, b.read_len, b.windows, stream)
+
+
+def hits_to_numpy(t) -> np.ndarray:
+    return t.cpu().numpy().view(HIT_DTYPE).reshape(-1)
+
+
+def aln_to_numpy(t) -> np.ndarray:
+    return t.cpu().numpy().view(ALN_DTYPE).reshape(-1)

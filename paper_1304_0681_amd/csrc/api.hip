@@ -1,0 +1,427 @@
+// C ABI: context, argument validation, scratch management and dispatch.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "internal.h"
+
+namespace hpgsw {
+
+const ClassShape kDefaultClasses[kNumClasses] = {
+    {16, 1, 16},  {32, 1, 32},  {64, 2, 32},    {100, 4, 25},   {128, 4, 32},   {160, 8, 20},
+    {256, 8, 32}, {512, 16, 32}, {1024, 32, 32}, {2048, 64, 32}, {65535, 64, 32}};
+
+int score_class_m_max(int cls) { return kDefaultClasses[cls].m_max; }
+
+}  // namespace hpgsw
+
+using namespace hpgsw;
+
+struct sw_ctx {
+    int device = 0;
+    int n_cu = 0;
+    std::string err;
+    // bucketing scratch
+    void *bscratch = nullptr;
+    size_t bscratch_bytes = 0;
+    // strip boundary rows of the score kernel (allocated on first use)
+    int2 *strip_buf = nullptr;
+    int strip_waves = 0;
+    // best-per-read keys
+    uint64_t *keys = nullptr;
+    size_t keys_n = 0;
+    // traceback code slots
+    uint32_t *tb = nullptr;
+    size_t tb_bytes = 0;
+    uint32_t *host_meta = nullptr;   // pinned: per-class segments and maxima
+    ClassShape shapes[kNumClasses];
+    int blocks_per_cu[kNumClasses];
+    // phase timing: ev[0] before bucketing, ev[1] after it, ev[2 + c] after class c
+    bool timing = false;
+    bool timed_call = false;
+    hipEvent_t ev[2 + kNumClasses] = {};
+};
+
+namespace {
+
+thread_local std::string g_noctx_err;
+
+sw_status fail(sw_ctx *ctx, sw_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+
+sw_status fail(sw_ctx *ctx, sw_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx)
+        ctx->err = buf;
+    else
+        g_noctx_err = buf;
+    return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                 \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? SW_E_NOMEM : SW_E_DEVICE,       \
+                        "%s: %s", #expr, hipGetErrorString(e_));                           \
+    } while (0)
+
+sw_status check_scoring(sw_ctx *ctx, const sw_scoring *sc)
+{
+    if (!sc)
+        return fail(ctx, SW_E_INVALID, "scoring is NULL");
+    if (sc->match <= 0 || sc->match > 127)
+        return fail(ctx, SW_E_INVALID, "match must be in [1, 127]");
+    if (sc->mismatch >= sc->match || sc->mismatch < -127)
+        return fail(ctx, SW_E_INVALID, "mismatch must be in [-127, match)");
+    if (sc->gap_open >= 0 || sc->gap_open < -127)
+        return fail(ctx, SW_E_INVALID, "gap_open must be in [-127, -1]");
+    if (sc->gap_extend > 0 || sc->gap_extend < sc->gap_open)
+        return fail(ctx, SW_E_INVALID, "gap_extend must be in [gap_open, 0]");
+    return SW_OK;
+}
+
+sw_status check_batch(sw_ctx *ctx, const sw_batch *b)
+{
+    if (!b)
+        return fail(ctx, SW_E_INVALID, "batch is NULL");
+    if (b->n_pairs == 0)
+        return SW_OK;
+    if (!b->d_win || !b->d_read_len || !b->d_read_off || !b->d_reads2b || !b->d_ref2b)
+        return fail(ctx, SW_E_INVALID, "batch has a NULL device pointer");
+    if (b->ref_len >= (1ull << 36))
+        return fail(ctx, SW_E_RANGE, "reference longer than 2^36 bases");
+    return SW_OK;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+sw_status ensure(sw_ctx *ctx, void **buf, size_t *have, size_t need)
+{
+    if (*have >= need)
+        return SW_OK;
+    const size_t old = *have;
+    if (*buf)
+        HIP_TRY(ctx, hipFree(*buf));
+    *buf = nullptr;
+    *have = 0;
+    size_t sz = std::max(need, old * 3 / 2);
+    HIP_TRY(ctx, hipMalloc(buf, sz));
+    *have = sz;
+    return SW_OK;
+}
+
+sw_status bucket_scratch(sw_ctx *ctx, uint32_t n_items, BucketScratch *s)
+{
+    const size_t n = std::max<uint32_t>(n_items, 1);
+    const size_t need = align_up(4 * n) * 2 + align_up(4 * kNumBins) + align_up(4 * 2 * kNumClasses) +
+                        align_up(4 * kNumClasses) + align_up(4 * 2 * kNumClasses);
+    sw_status st = ensure(ctx, &ctx->bscratch, &ctx->bscratch_bytes, need);
+    if (st)
+        return st;
+    char *p = static_cast<char *>(ctx->bscratch);
+    s->bin = reinterpret_cast<uint32_t *>(p);
+    p += align_up(4 * n);
+    s->ids = reinterpret_cast<uint32_t *>(p);
+    p += align_up(4 * n);
+    s->hist = reinterpret_cast<uint32_t *>(p);
+    p += align_up(4 * kNumBins);
+    s->seg = reinterpret_cast<uint32_t *>(p);
+    p += align_up(4 * 2 * kNumClasses);
+    s->counter = reinterpret_cast<uint32_t *>(p);
+    p += align_up(4 * kNumClasses);
+    s->maxlen = reinterpret_cast<uint32_t *>(p);
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sw_status sw_ctx_create(int hip_device, sw_ctx **out)
+{
+    if (!out)
+        return fail(nullptr, SW_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0)
+        return fail(nullptr, SW_E_NODEVICE, "no HIP device");
+    if (hip_device < 0 || hip_device >= n)
+        return fail(nullptr, SW_E_NODEVICE, "device %d does not exist (%d devices)", hip_device, n);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess)
+        return fail(nullptr, SW_E_NODEVICE, "cannot query device %d", hip_device);
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, SW_E_NODEVICE, "device %d is %s, not gfx950", hip_device,
+                    prop.gcnArchName);
+    sw_ctx *ctx = new sw_ctx;
+    ctx->device = hip_device;
+    ctx->n_cu = prop.multiProcessorCount;
+    for (int c = 0; c < kNumClasses; ++c) {
+        ctx->shapes[c] = kDefaultClasses[c];
+        ctx->blocks_per_cu[c] = 2;
+    }
+    if (hipSetDevice(hip_device) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&ctx->host_meta), 4 * 4 * kNumClasses) != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, SW_E_DEVICE, "device set-up failed");
+    }
+    *out = ctx;
+    return SW_OK;
+}
+
+sw_status sw_ctx_destroy(sw_ctx *ctx)
+{
+    if (!ctx)
+        return SW_E_INVALID;
+    hipError_t e = hipSetDevice(ctx->device);
+    auto keep = [&e](hipError_t x) { if (e == hipSuccess) e = x; };
+    keep(hipDeviceSynchronize());
+    if (ctx->bscratch) keep(hipFree(ctx->bscratch));
+    if (ctx->strip_buf) keep(hipFree(ctx->strip_buf));
+    if (ctx->keys) keep(hipFree(ctx->keys));
+    if (ctx->tb) keep(hipFree(ctx->tb));
+    if (ctx->host_meta) keep(hipHostFree(ctx->host_meta));
+    for (auto &ev : ctx->ev)
+        if (ev) keep(hipEventDestroy(ev));
+    delete ctx;
+    if (e != hipSuccess)
+        return fail(nullptr, SW_E_DEVICE, "sw_ctx_destroy: %s", hipGetErrorString(e));
+    return SW_OK;
+}
+
+const char *sw_last_error(const sw_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_noctx_err.c_str();
+}
+
+sw_status sw_pack2b(sw_ctx *ctx, const uint8_t *d_ascii, uint64_t n, uint32_t *d_out,
+                    uint32_t *d_bad, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    if (n == 0)
+        return SW_OK;
+    if (!d_ascii || !d_out)
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_pack2b(d_ascii, n, d_out, d_bad, static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint32_t flags,
+                         sw_hit *d_hits, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    sw_status st = check_batch(ctx, b);
+    if (st)
+        return st;
+    if ((st = check_scoring(ctx, sc)))
+        return st;
+    if (flags & ~SW_WANT_ENDS)
+        return fail(ctx, SW_E_INVALID, "unknown flags 0x%x", flags);
+    if (b->n_pairs == 0)
+        return SW_OK;
+    if (!d_hits)
+        return fail(ctx, SW_E_INVALID, "d_hits is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    BucketScratch bs;
+    if ((st = bucket_scratch(ctx, b->n_pairs, &bs)))
+        return st;
+    // strip buffers only when some read may exceed the largest single-strip class
+    const bool may_strip = b->reads_len > (uint64_t)kDefaultClasses[kNumClasses - 2].m_max;
+    if (may_strip && !ctx->strip_buf) {
+        ctx->strip_waves = 64;
+        HIP_TRY(ctx, hipMalloc(reinterpret_cast<void **>(&ctx->strip_buf),
+                               sizeof(int2) * 65536ull * (size_t)ctx->strip_waves));
+    }
+    if (ctx->timing)
+        HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
+    HIP_TRY(ctx, launch_bucket(*b, nullptr, b->n_pairs, bs, d_hits, nullptr, s));
+    if (ctx->timing)
+        HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
+    ScoreParams p;
+    p.ref = b->d_ref2b;
+    p.ref_len = b->ref_len;
+    p.ref_words = (b->ref_len + 15) / 16;
+    p.reads = b->d_reads2b;
+    p.read_words = (b->reads_len + 15) / 16;
+    p.read_off = b->d_read_off;
+    p.read_len = b->d_read_len;
+    p.win = b->d_win;
+    p.ids = bs.ids;
+    p.seg = bs.seg;
+    p.counter = bs.counter;
+    p.ma = sc->match;
+    p.mi = sc->mismatch;
+    p.go = sc->gap_open;
+    p.ge = sc->gap_extend;
+    p.hits = d_hits;
+    p.strip_buf = ctx->strip_buf;
+    p.strip_stride = 65536;
+    const bool ends = flags & SW_WANT_ENDS;
+    for (int c = 0; c < kNumClasses; ++c) {
+        const bool strip = c == kNumClasses - 1;
+        const bool skip = (strip && !may_strip) ||
+                          (!strip && c > 0 && (uint64_t)kDefaultClasses[c - 1].m_max >= b->reads_len);
+        if (skip) {     // no read of this batch can fall in this class
+            if (ctx->timing)
+                HIP_TRY(ctx, hipEventRecord(ctx->ev[2 + c], s));
+            continue;
+        }
+        p.cls = c;
+        const bool wide = (int64_t)sc->match * kDefaultClasses[c].m_max >= 32768;
+        const int mode = ends ? (wide ? 2 : 1) : 0;
+        const int wpb = score_waves_per_block();
+        const int grid = strip ? ctx->strip_waves / wpb : ctx->n_cu * ctx->blocks_per_cu[c];
+        HIP_TRY(ctx, launch_score_class(c, ctx->shapes[c].G, ctx->shapes[c].RPL, mode, p, grid, s));
+        if (ctx->timing)
+            HIP_TRY(ctx, hipEventRecord(ctx->ev[2 + c], s));
+    }
+    ctx->timed_call = ctx->timing;
+    return SW_OK;
+}
+
+sw_status sw_best_per_read(sw_ctx *ctx, const sw_batch *b, const sw_hit *d_hits, int32_t t_map,
+                           uint32_t *d_best_pair, int32_t *d_best_score, uint8_t *d_mapped,
+                           void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    sw_status st = check_batch(ctx, b);
+    if (st)
+        return st;
+    if (b->n_reads == 0)
+        return SW_OK;
+    if ((b->n_pairs && !d_hits) || !d_best_pair || !d_best_score)
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    size_t have = ctx->keys_n * 8;
+    void *buf = ctx->keys;
+    if ((st = ensure(ctx, &buf, &have, 8ull * b->n_reads)))
+        return st;
+    ctx->keys = static_cast<uint64_t *>(buf);
+    ctx->keys_n = have / 8;
+    HIP_TRY(ctx, launch_best(*b, d_hits, ctx->keys, t_map, d_best_pair, d_best_score, d_mapped,
+                             static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc,
+                             const uint32_t *d_pair_ids, uint32_t n_sel, sw_aln *d_aln,
+                             uint32_t *d_ops, uint32_t ops_stride, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    sw_status st = check_batch(ctx, b);
+    if (st)
+        return st;
+    if ((st = check_scoring(ctx, sc)))
+        return st;
+    if (n_sel == 0)
+        return SW_OK;
+    if (!d_pair_ids || !d_aln || (!d_ops && ops_stride))
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    if (b->n_pairs == 0)
+        return fail(ctx, SW_E_INVALID, "pair ids given for an empty batch");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    BucketScratch bs;
+    if ((st = bucket_scratch(ctx, n_sel, &bs)))
+        return st;
+    HIP_TRY(ctx, launch_bucket(*b, d_pair_ids, n_sel, bs, nullptr, d_aln, s));
+    // size the code slots from the per-class maxima (one stream synchronisation)
+    uint32_t *meta = ctx->host_meta;
+    HIP_TRY(ctx, hipMemcpyAsync(meta, bs.seg, 4 * 2 * kNumClasses, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(meta + 2 * kNumClasses, bs.maxlen, 4 * 2 * kNumClasses,
+                                hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    for (int c = 0; c < kNumClasses; ++c) {
+        const uint32_t count = meta[2 * c + 1] - meta[2 * c];
+        if (count == 0)
+            continue;
+        const uint64_t nmax = meta[2 * kNumClasses + c];
+        const uint64_t mmax = meta[3 * kNumClasses + c];
+        const uint64_t sr = (uint64_t)traceback_rows_cap(c);
+        const bool strip = c == kNumClasses - 1;
+        const uint64_t rows_cap = strip ? (mmax + sr - 1) / sr * sr : sr;
+        const uint64_t slot_words = rows_cap / 8 * nmax + (strip ? 2 * nmax : 0) + mmax + nmax + 8;
+        const int ppw = traceback_pairs_per_wave(c);
+        const int wpb = traceback_waves_per_block();
+        uint64_t waves = std::min<uint64_t>((count + ppw - 1) / ppw, (uint64_t)ctx->n_cu * 8);
+        const uint64_t budget = 4ull << 30;   // bytes of code slots at most
+        while (waves > (uint64_t)wpb && waves * ppw * slot_words * 4 > budget)
+            waves /= 2;
+        const uint64_t blocks = (waves + wpb - 1) / wpb;
+        const uint64_t need = blocks * wpb * ppw * slot_words * 4;
+        void *buf = ctx->tb;
+        size_t have = ctx->tb_bytes;
+        if ((st = ensure(ctx, &buf, &have, need)))
+            return st;
+        ctx->tb = static_cast<uint32_t *>(buf);
+        ctx->tb_bytes = have;
+        HIP_TRY(ctx, launch_traceback_class(c, *b, *sc, d_pair_ids, bs.ids, bs.seg, bs.counter,
+                                            d_aln, d_ops, ops_stride, ctx->tb, slot_words,
+                                            (int)blocks, s));
+    }
+    return SW_OK;
+}
+
+sw_status sw_timing_enable(sw_ctx *ctx, int on)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (on && !ctx->ev[0])
+        for (auto &e : ctx->ev)
+            HIP_TRY(ctx, hipEventCreate(&e));
+    ctx->timing = on != 0;
+    ctx->timed_call = false;
+    return SW_OK;
+}
+
+sw_status sw_timing_get(sw_ctx *ctx, sw_timing *out)
+{
+    if (!ctx || !out)
+        return fail(ctx, SW_E_INVALID, "NULL argument");
+    if (!ctx->timing || !ctx->timed_call)
+        return fail(ctx, SW_E_STATE, "no timed sw_batch_score call");
+    HIP_TRY(ctx, hipEventSynchronize(ctx->ev[1 + kNumClasses]));
+    memset(out, 0, sizeof *out);
+    HIP_TRY(ctx, hipEventElapsedTime(&out->bucket_ms, ctx->ev[0], ctx->ev[1]));
+    for (int c = 0; c < kNumClasses; ++c) {
+        HIP_TRY(ctx, hipEventElapsedTime(&out->class_ms[c], ctx->ev[1 + c], ctx->ev[2 + c]));
+        out->score_ms += out->class_ms[c];
+    }
+    return SW_OK;
+}
+
+int sw_cigar_string(const uint32_t *ops, uint32_t n_ops, char *buf, uint32_t cap)
+{
+    static const char names[] = "MIDNS";
+    if (!buf || cap == 0)
+        return -1;
+    uint32_t k = 0;
+    for (uint32_t i = 0; i < n_ops; ++i) {
+        const uint32_t code = ops[i] & 15u;
+        char tmp[24];
+        const int len = snprintf(tmp, sizeof tmp, "%u%c", ops[i] >> 4, code < 5 ? names[code] : '?');
+        if (k + (uint32_t)len + 1 > cap)
+            return -1;
+        memcpy(buf + k, tmp, (size_t)len);
+        k += (uint32_t)len;
+    }
+    buf[k] = 0;
+    return (int)k;
+}
+
+}  // extern "C"

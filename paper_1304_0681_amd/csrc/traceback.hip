@@ -1,0 +1,404 @@
+// Traceback: full alignments with CIGAR for selected pairs.
+//
+// The DP of the score kernel is recomputed with the same lane layout (G lanes
+// per pair, RPL rows per lane, RPL a multiple of 8).  Every cell stores a
+// 4-bit direction code in a per-pair slot of device scratch:
+//   bits 0-1  H source: 0 stop (H == 0), 1 diagonal, 2 deletion (E), 3 insertion
+//             (first true in that order)
+//   bit 2     the deletion value of the NEXT column extends rather than opens
+//             (E(i,c) + gap_extend > H(i,c) + gap_open)
+//   bit 3     the insertion value of the NEXT row extends rather than opens
+// Column c stores its rows contiguously (8 codes per 32-bit word), so each
+// lane writes RPL/8 whole words per step.  The first lane of each group then
+// walks back from the end cell (smallest window column, then smallest read row
+// among the maxima) under the canonical rule and run-length encodes the ops.
+#include "internal.h"
+
+namespace hpgsw {
+
+namespace {
+
+constexpr int kWaves = 4;
+
+struct TBParams {
+    const uint32_t *ref;
+    uint64_t ref_len, ref_words;
+    const uint32_t *reads;
+    const uint64_t *read_off;
+    const uint16_t *read_len;
+    uint32_t n_reads;
+    const sw_window *win;
+    const uint32_t *sel;       // caller's selected pair ids
+    const uint32_t *ids;       // indices into sel, bucketed
+    const uint32_t *seg;
+    uint32_t *counter;
+    int cls;
+    int ma, mi, go, ge;
+    sw_aln *aln;
+    uint32_t *ops;
+    uint32_t ops_stride;
+    uint32_t *codes;           // scratch: per group slot
+    uint64_t slot_words;       // words per group slot
+};
+
+template <int G>
+__device__ __forceinline__ int tb_shift_up(int x, bool first, int boundary)
+{
+    if constexpr (G == 16) {
+        return __builtin_amdgcn_update_dpp(boundary, x, 0x111, 0xF, 0xF, false);
+    } else if constexpr (G == 64) {
+        return __builtin_amdgcn_update_dpp(boundary, x, 0x138, 0xF, 0xF, false);
+    } else if constexpr (G == 32) {
+        int y = __builtin_amdgcn_update_dpp(boundary, x, 0x138, 0xF, 0xF, false);
+        return first ? boundary : y;
+    } else {
+        int y = __builtin_amdgcn_update_dpp(boundary, x, 0x111, 0xF, 0xF, false);
+        return first ? boundary : y;
+    }
+}
+
+__device__ __forceinline__ int tb_wave_max(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v = max(v, __shfl_xor(v, off));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t tb_window_word(const TBParams &P, int64_t rb, int64_t c0)
+{
+    const int64_t s = rb + c0;   // reference position of column c0
+    if (s < 0) {
+        // columns before the reference start are masked; the rest begin at base 0
+        if (s <= -16)
+            return 0u;
+        return P.ref[0] << (2u * (uint32_t)(-s));
+    }
+    uint64_t w0 = (uint64_t)s >> 4;
+    uint64_t w1 = w0 + 1;
+    const uint64_t last = P.ref_words - 1;
+    if (w0 > last) w0 = last;   // only columns past the reference end read these
+    if (w1 > last) w1 = last;
+    return __builtin_amdgcn_alignbit(P.ref[w1], P.ref[w0], (uint32_t)(s & 15) * 2u);
+}
+
+// STRIP: queries longer than one strip of G*RPL rows (G == 64); the boundary
+// row between strips goes through the tail of the pair's slot.
+template <int G, int RPL, bool STRIP>
+__global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
+{
+    static_assert(RPL % 8 == 0, "codes are stored 8 per word");
+    constexpr int PPW = 64 / G;
+    constexpr int SR = G * RPL;
+    constexpr int WPL = RPL / 8;   // code words per lane per column
+    const int lane = threadIdx.x & 63;
+    const int grp = lane / G;
+    const int l = lane % G;
+    const bool first = l == 0;
+    const uint32_t seg_begin = P.seg[2 * P.cls];
+    const uint32_t seg_end = P.seg[2 * P.cls + 1];
+    const uint32_t n_tasks = (seg_end - seg_begin + PPW - 1) / PPW;
+    const int go = P.go, ge = P.ge;
+    const uint32_t wave_global = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    uint32_t *slot_codes = P.codes + (uint64_t)(wave_global * PPW + grp) * P.slot_words;
+
+    for (;;) {
+        uint32_t task = 0;
+        if (lane == 0)
+            task = atomicAdd(&P.counter[P.cls], 1u);
+        task = __shfl(task, 0);
+        if (task >= n_tasks)
+            break;
+        const uint32_t slot = seg_begin + task * PPW + grp;
+        const bool active = slot < seg_end;
+        const uint32_t k_sel = active ? P.ids[slot] : 0u;
+        const uint32_t pair = P.sel[k_sel];
+        const sw_window w = P.win[pair];
+        int m = 0, n = 0;
+        uint64_t roff = 0;
+        if (active) {
+            m = P.read_len[w.read_id];
+            roff = P.read_off[w.read_id];
+            const uint64_t avail = P.ref_len - w.ref_begin;
+            n = w.len < avail ? (int)w.len : (int)avail;
+        }
+        const int n_wave = tb_wave_max(n);
+        const int T = n_wave + G - 1;
+        const int m_wave = STRIP ? tb_wave_max(m) : SR;
+        const int n_strips = STRIP ? (m_wave + SR - 1) / SR : 1;
+        const int rows_cap = n_strips * SR;          // rows stored per column
+        const uint32_t col_words = (uint32_t)rows_cap / 8;
+        const uint64_t code_words = (uint64_t)col_words * (uint64_t)n_wave;
+        int2 *bnd = reinterpret_cast<int2 *>(slot_codes + code_words);  // strip boundary row
+        uint32_t *runs = slot_codes + code_words + (STRIP ? 2 * (uint64_t)n_wave : 0);
+        const int64_t rb = (int64_t)w.ref_begin;
+
+        int best = 0, cbest = 0x7FFFFFFF, rbest = 0x7FFFFFFF;
+
+        for (int strip = 0; strip < n_strips; ++strip) {
+            const int row0 = strip * SR + l * RPL;
+            int prof[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = row0 + r;
+                if (i < m) {
+                    const uint64_t pos = w.strand ? roff + (uint64_t)(m - 1 - i) : roff + (uint64_t)i;
+                    uint32_t q = (P.reads[pos >> 4] >> (2 * (uint32_t)(pos & 15))) & 3u;
+                    if (w.strand)
+                        q = 3u - q;
+                    uint32_t v = 0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        v |= ((uint32_t)(b == (int)q ? P.ma : P.mi) & 0xFFu) << (8 * b);
+                    prof[r] = (int)v;
+                } else {
+                    prof[r] = (int)0x80808080u;
+                }
+            }
+            int H[RPL], E[RPL], bh[RPL], bj[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                H[r] = 0;
+                E[r] = go;
+                bh[r] = 0;
+                bj[r] = 0x7FFFFFFF;
+            }
+            int hup_prev = 0, gout = 0;
+            const bool read_bnd = STRIP && strip > 0;
+            const bool write_bnd = STRIP && strip + 1 < n_strips;
+            __threadfence_block();
+            uint32_t cur = tb_window_word(P, rb, -l);
+            for (int t0 = 0; t0 < T; t0 += 16) {
+                const uint32_t nxt = tb_window_word(P, rb, t0 + 16 - l);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int t = t0 + k;
+                    if (t >= T)
+                        break;
+                    const int c = t - l;
+                    const bool valid = (unsigned)c < (unsigned)n;
+                    const int wd = valid ? 8 : 0;
+                    const int rc8 = (int)((cur >> (2 * k)) & 3u) << 3;
+                    int bh_in = 0, bg_in = 0;
+                    if (read_bnd && first && (unsigned)t < (unsigned)n_wave) {
+                        const int2 v = bnd[t];
+                        bh_in = v.x;
+                        bg_in = v.y;
+                    }
+                    const int hup = tb_shift_up<G>(H[RPL - 1], first, bh_in);
+                    const int gin = tb_shift_up<G>(gout, first, bg_in);
+                    int diag = hup_prev;
+                    hup_prev = hup;
+                    int g = gin;
+                    uint32_t cw[WPL];
+#pragma unroll
+                    for (int q = 0; q < WPL; ++q)
+                        cw[q] = 0;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) {
+                        const int s = __builtin_amdgcn_sbfe(prof[r], rc8, wd);
+                        const int dd = diag + s;
+                        diag = H[r];
+                        const int e = E[r];
+                        const int h = max(max(dd, e), g);
+                        const uint32_t src = h == 0 ? 0u : (h == dd ? 1u : (h == e ? 2u : 3u));
+                        H[r] = h;
+                        const int hg = h + go;
+                        const uint32_t eext = (e + ge > hg) ? 4u : 0u;
+                        const uint32_t fext = (g + ge > hg) ? 8u : 0u;
+                        E[r] = max(e + ge, hg);
+                        g = max(max(g + ge, hg), 0);
+                        cw[r >> 3] |= (src | eext | fext) << (4 * (r & 7));
+                        const bool better = valid && h > bh[r];
+                        bh[r] = better ? h : bh[r];
+                        bj[r] = better ? c : bj[r];
+                    }
+                    gout = g;
+                    if (valid) {
+                        uint32_t *dst = slot_codes + (uint64_t)c * col_words + (uint32_t)(row0 >> 3);
+#pragma unroll
+                        for (int q = 0; q < WPL; ++q)
+                            dst[q] = cw[q];
+                        if (write_bnd && l == G - 1)
+                            bnd[c] = make_int2(H[RPL - 1], g);
+                    }
+                }
+                cur = nxt;
+            }
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int row = row0 + r;
+                const bool better = bh[r] > best ||
+                                    (bh[r] == best && bh[r] > 0 &&
+                                     (bj[r] < cbest || (bj[r] == cbest && row < rbest)));
+                if (better) {
+                    best = bh[r];
+                    cbest = bj[r];
+                    rbest = row;
+                }
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) {
+            const int ob = __shfl_xor(best, off);
+            const int oc = __shfl_xor(cbest, off);
+            const int orow = __shfl_xor(rbest, off);
+            const bool take = ob > best || (ob == best && (oc < cbest || (oc == cbest && orow < rbest)));
+            best = take ? ob : best;
+            cbest = take ? oc : cbest;
+            rbest = take ? orow : rbest;
+        }
+        __threadfence_block();   // code stores of the whole wave before the walk
+
+        if (active && first) {
+            sw_aln a;
+            a.status = 0;
+            uint32_t *out = P.ops + (uint64_t)k_sel * P.ops_stride;
+            if (best <= 0) {
+                a.score = 0;
+                a.read_begin = a.read_end = a.ref_begin = a.ref_end = -1;
+                a.n_ops = 0;
+            } else {
+                // walk back; runs are collected last-to-first in `runs`
+                int i = rbest, c = cbest, state = 0, bi = rbest, bc = cbest;
+                uint32_t nruns = 0, cur_op = 0xFFu, cur_len = 0;
+                auto code_at = [&](int ii, int cc) -> uint32_t {
+                    const uint32_t wv = slot_codes[(uint64_t)cc * col_words + (uint32_t)(ii >> 3)];
+                    return (wv >> (4 * (ii & 7))) & 15u;
+                };
+                const uint32_t max_runs = (uint32_t)(m + n + 2);
+                auto emit = [&](uint32_t op) {
+                    if (op == cur_op) {
+                        ++cur_len;
+                    } else {
+                        if (cur_len && nruns < max_runs)
+                            runs[nruns++] = (cur_len << 4) | cur_op;
+                        cur_op = op;
+                        cur_len = 1;
+                    }
+                };
+                for (;;) {
+                    if (state == 0) {
+                        if (i < 0 || c < 0)
+                            break;
+                        const uint32_t src = code_at(i, c) & 3u;
+                        if (src == 0)
+                            break;
+                        if (src == 1) {
+                            emit(SW_OP_M);
+                            bi = i;
+                            bc = c;
+                            --i;
+                            --c;
+                        } else {
+                            state = (int)src - 1;   // 1: deletion run, 2: insertion run
+                        }
+                    } else if (state == 1) {
+                        emit(SW_OP_D);
+                        const uint32_t ext = c > 0 ? (code_at(i, c - 1) >> 2) & 1u : 0u;
+                        --c;
+                        if (!ext)
+                            state = 0;
+                    } else {
+                        emit(SW_OP_I);
+                        const uint32_t ext = i > 0 ? (code_at(i - 1, c) >> 3) & 1u : 0u;
+                        --i;
+                        if (!ext)
+                            state = 0;
+                    }
+                }
+                if (cur_len && nruns < max_runs)
+                    runs[nruns++] = (cur_len << 4) | cur_op;
+                a.score = best;
+                a.read_begin = bi;
+                a.read_end = rbest;
+                a.ref_begin = bc;
+                a.ref_end = cbest;
+                uint32_t k = 0;
+                bool trunc = false;
+                auto put = [&](uint32_t v) {
+                    if (k < P.ops_stride)
+                        out[k] = v;
+                    else
+                        trunc = true;
+                    ++k;
+                };
+                if (bi > 0)
+                    put(((uint32_t)bi << 4) | SW_OP_S);
+                for (int q = (int)nruns - 1; q >= 0; --q)
+                    put(runs[q]);
+                if (m - 1 - rbest > 0)
+                    put(((uint32_t)(m - 1 - rbest) << 4) | SW_OP_S);
+                a.n_ops = trunc ? P.ops_stride : k;
+                if (trunc)
+                    a.status |= 1u;
+            }
+            P.aln[k_sel] = a;
+        }
+        __threadfence_block();   // the walk's reads finish before the slot is reused
+    }
+}
+
+template <int G, int RPL, bool STRIP>
+hipError_t tb_launch(const TBParams &p, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_sw_traceback<G, RPL, STRIP>), dim3(grid), dim3(64 * kWaves), 0, st, p);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Traceback shapes per query-length class (RPL a multiple of 8).
+static const ClassShape kTBShapes[kNumClasses] = {
+    {16, 2, 8},   {32, 2, 16},  {64, 4, 16},   {100, 8, 16},  {128, 8, 16},  {160, 16, 16},
+    {256, 16, 16}, {512, 16, 32}, {1024, 32, 32}, {2048, 64, 32}, {65535, 64, 32}};
+
+int traceback_rows_cap(int cls) { return kTBShapes[cls].G * kTBShapes[cls].RPL; }
+int traceback_pairs_per_wave(int cls) { return 64 / kTBShapes[cls].G; }
+int traceback_waves_per_block() { return kWaves; }
+
+hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &sc,
+                                  const uint32_t *sel, const uint32_t *ids, const uint32_t *seg,
+                                  uint32_t *counter, sw_aln *aln, uint32_t *ops,
+                                  uint32_t ops_stride, uint32_t *codes, uint64_t slot_words,
+                                  int grid, hipStream_t st)
+{
+    TBParams p;
+    p.ref = b.d_ref2b;
+    p.ref_len = b.ref_len;
+    p.ref_words = (b.ref_len + 15) / 16;
+    p.reads = b.d_reads2b;
+    p.read_off = b.d_read_off;
+    p.read_len = b.d_read_len;
+    p.n_reads = b.n_reads;
+    p.win = b.d_win;
+    p.sel = sel;
+    p.ids = ids;
+    p.seg = seg;
+    p.counter = counter;
+    p.cls = cls;
+    p.ma = sc.match;
+    p.mi = sc.mismatch;
+    p.go = sc.gap_open;
+    p.ge = sc.gap_extend;
+    p.aln = aln;
+    p.ops = ops;
+    p.ops_stride = ops_stride;
+    p.codes = codes;
+    p.slot_words = slot_words;
+    switch (cls) {
+    case 0: return tb_launch<2, 8, false>(p, grid, st);
+    case 1: return tb_launch<2, 16, false>(p, grid, st);
+    case 2: return tb_launch<4, 16, false>(p, grid, st);
+    case 3: return tb_launch<8, 16, false>(p, grid, st);
+    case 4: return tb_launch<8, 16, false>(p, grid, st);
+    case 5: return tb_launch<16, 16, false>(p, grid, st);
+    case 6: return tb_launch<16, 16, false>(p, grid, st);
+    case 7: return tb_launch<16, 32, false>(p, grid, st);
+    case 8: return tb_launch<32, 32, false>(p, grid, st);
+    case 9: return tb_launch<64, 32, false>(p, grid, st);
+    default: return tb_launch<64, 32, true>(p, grid, st);
+    }
+}
+
+}  // namespace hpgsw
