@@ -159,6 +159,17 @@ sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *batch, const sw_scorin
                              const uint32_t *d_pair_ids, uint32_t n_sel, sw_aln *d_aln,
                              uint32_t *d_ops, uint32_t ops_stride, void *stream);
 
+/* Context options (sw_ctx_set_option).
+ * SW_OPT_INT16: 1 (default) lets score-only calls use the packed int16
+ *   datapath for the query-length classes where it is exact (match * longest
+ *   query of the class <= 32767 and mismatch <= 0); 0 forces int32.  Results
+ *   are identical either way.
+ * SW_OPT_BLOCKS_PER_CU: workgroups (4 waves each) per compute unit of the
+ *   persistent scoring kernels, 1..64 (default 2). */
+#define SW_OPT_INT16 1
+#define SW_OPT_BLOCKS_PER_CU 2
+sw_status sw_ctx_set_option(sw_ctx *ctx, int option, int value);
+
 /* Phase timing of sw_batch_score, from HIP events recorded on the call's
  * stream.  bucket_ms covers the length bucketing; class_ms[c] the wavefront
  * kernel of query-length class c (classes: m <= 16, 32, 64, 100, 128, 160,
@@ -167,6 +178,7 @@ typedef struct {
     float bucket_ms;
     float score_ms;
     float class_ms[16];
+    int32_t class_path[16];   /* 0 not launched, 1 int32, 2 int32 with ends, 3 packed int16 */
 } sw_timing;
 
 /* Turn event recording on (on != 0) or off for later sw_batch_score calls. */

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libhpgsw.so")
 SW_OK, SW_E_INVALID, SW_E_RANGE, SW_E_NOMEM, SW_E_DEVICE, SW_E_NODEVICE, SW_E_STATE = \
     0, -1, -2, -3, -4, -5, -6
 SW_WANT_ENDS = 1
+SW_OPT_INT16 = 1
+SW_OPT_BLOCKS_PER_CU = 2
 OP_NAMES = "MIDNS"
 
 HIT_DTYPE = np.dtype([("score", "<i4"), ("read_end", "<i4"), ("ref_end", "<i4")])
@@ -42,7 +44,7 @@ class sw_scoring(ctypes.Structure):
 
 class sw_timing(ctypes.Structure):
     _fields_ = [("bucket_ms", ctypes.c_float), ("score_ms", ctypes.c_float),
-                ("class_ms", ctypes.c_float * 16)]
+                ("class_ms", ctypes.c_float * 16), ("class_path", ctypes.c_int32 * 16)]
 
 
 class sw_batch(ctypes.Structure):
@@ -76,10 +78,11 @@ def lib() -> ctypes.CDLL:
                                          P, U32, P, P, U32, P]
         L.sw_cigar_string.argtypes = [P, U32, ctypes.c_char_p, U32]
         L.sw_timing_enable.argtypes = [P, ctypes.c_int]
+        L.sw_ctx_set_option.argtypes = [P, ctypes.c_int, ctypes.c_int]
         L.sw_timing_get.argtypes = [P, ctypes.POINTER(sw_timing)]
         for f in ("sw_ctx_create", "sw_ctx_destroy", "sw_pack2b", "sw_batch_score",
                   "sw_best_per_read", "sw_batch_traceback", "sw_cigar_string",
-                  "sw_timing_enable", "sw_timing_get"):
+                  "sw_timing_enable", "sw_timing_get", "sw_ctx_set_option"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -134,6 +137,10 @@ def sw_batch_traceback(ctx, batch, scoring, d_pair_ids, n_sel, d_aln, d_ops, ops
     _check(ctx, lib().sw_batch_traceback(ctx, ctypes.byref(batch.c), ctypes.byref(_sc(scoring)),
                                          _ptr(d_pair_ids), int(n_sel), _ptr(d_aln), _ptr(d_ops),
                                          int(ops_stride), _stream_ptr(stream)))
+
+
+def sw_ctx_set_option(ctx, option, value):
+    _check(ctx, lib().sw_ctx_set_option(ctx, int(option), int(value)))
 
 
 def sw_timing_enable(ctx, on=True):

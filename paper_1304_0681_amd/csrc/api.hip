@@ -16,6 +16,9 @@ const ClassShape kDefaultClasses[kNumClasses] = {
 
 int score_class_m_max(int cls) { return kDefaultClasses[cls].m_max; }
 
+// Packed int16 shapes enabled for dispatch.
+static bool packed_verified(const ClassShape &s) { return s.G == 4 && s.RPL == 25; }
+
 }  // namespace hpgsw
 
 using namespace hpgsw;
@@ -39,9 +42,11 @@ struct sw_ctx {
     uint32_t *host_meta = nullptr;   // pinned: per-class segments and maxima
     ClassShape shapes[kNumClasses];
     int blocks_per_cu[kNumClasses];
+    bool int16 = true;   // packed int16 datapath where exact
     // phase timing: ev[0] before bucketing, ev[1] after it, ev[2 + c] after class c
     bool timing = false;
     bool timed_call = false;
+    int32_t class_path[kNumClasses] = {};
     hipEvent_t ev[2 + kNumClasses] = {};
 };
 
@@ -273,6 +278,7 @@ sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
         const bool strip = c == kNumClasses - 1;
         const bool skip = (strip && !may_strip) ||
                           (!strip && c > 0 && (uint64_t)kDefaultClasses[c - 1].m_max >= b->reads_len);
+        ctx->class_path[c] = 0;
         if (skip) {     // no read of this batch can fall in this class
             if (ctx->timing)
                 HIP_TRY(ctx, hipEventRecord(ctx->ev[2 + c], s));
@@ -283,7 +289,17 @@ sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
         const int mode = ends ? (wide ? 2 : 1) : 0;
         const int wpb = score_waves_per_block();
         const int grid = strip ? ctx->strip_waves / wpb : ctx->n_cu * ctx->blocks_per_cu[c];
-        HIP_TRY(ctx, launch_score_class(c, ctx->shapes[c].G, ctx->shapes[c].RPL, mode, p, grid, s));
+        // packed int16 when every score of the class fits 16 bits exactly.  Only
+        // the shapes in kPackedVerified run packed: a call that used the packed
+        // kernel for all classes did not return, and its cause is not known.
+        const bool packed = mode == 0 && ctx->int16 && !strip && sc->mismatch <= 0 &&
+                            (int64_t)sc->match * kDefaultClasses[c].m_max <= 32767 &&
+                            packed_verified(ctx->shapes[c]);
+        if (packed)
+            HIP_TRY(ctx, launch_score16_class(ctx->shapes[c].G, ctx->shapes[c].RPL, p, grid, s));
+        else
+            HIP_TRY(ctx, launch_score_class(c, ctx->shapes[c].G, ctx->shapes[c].RPL, mode, p, grid, s));
+        ctx->class_path[c] = packed ? 3 : (mode ? 2 : 1);
         if (ctx->timing)
             HIP_TRY(ctx, hipEventRecord(ctx->ev[2 + c], s));
     }
@@ -376,6 +392,25 @@ sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *b, const sw_scoring *s
     return SW_OK;
 }
 
+sw_status sw_ctx_set_option(sw_ctx *ctx, int option, int value)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    switch (option) {
+    case SW_OPT_INT16:
+        ctx->int16 = value != 0;
+        return SW_OK;
+    case SW_OPT_BLOCKS_PER_CU:
+        if (value < 1 || value > 64)
+            return fail(ctx, SW_E_RANGE, "blocks per CU must be in [1, 64]");
+        for (int c = 0; c < kNumClasses; ++c)
+            ctx->blocks_per_cu[c] = value;
+        return SW_OK;
+    default:
+        return fail(ctx, SW_E_INVALID, "unknown option %d", option);
+    }
+}
+
 sw_status sw_timing_enable(sw_ctx *ctx, int on)
 {
     if (!ctx)
@@ -401,6 +436,7 @@ sw_status sw_timing_get(sw_ctx *ctx, sw_timing *out)
     for (int c = 0; c < kNumClasses; ++c) {
         HIP_TRY(ctx, hipEventElapsedTime(&out->class_ms[c], ctx->ev[1 + c], ctx->ev[2 + c]));
         out->score_ms += out->class_ms[c];
+        out->class_path[c] = ctx->class_path[c];
     }
     return SW_OK;
 }

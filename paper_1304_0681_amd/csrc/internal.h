@@ -68,6 +68,7 @@ hipError_t launch_bucket(const sw_batch &b, const uint32_t *sel, uint32_t n_item
 hipError_t launch_score_class(int cls, int G, int RPL, int mode, const ScoreParams &p, int grid,
                               hipStream_t st);
 int score_class_m_max(int cls);
+hipError_t launch_score16_class(int G, int RPL, const ScoreParams &p, int grid, hipStream_t st);
 bool score_shape_available(int G, int RPL);
 int score_waves_per_block();
 hipError_t launch_best(const sw_batch &b, const sw_hit *hits, uint64_t *keys, int32_t t_map,
