@@ -92,6 +92,10 @@ typedef struct {
     uint32_t n_reads;
     const sw_window *d_win;       /* [n_pairs] windows, any order */
     uint32_t n_pairs;
+    /* optional device count of valid pairs: when not NULL, only the first
+     * min(n_pairs, *d_n_pairs) windows are used and n_pairs is the capacity
+     * (lets a compacted work list be scored without a host round trip) */
+    const uint32_t *d_n_pairs;
 } sw_batch;
 
 /* Score result of one pair.  score -1 marks an invalid pair (read_id out of
@@ -158,6 +162,81 @@ sw_status sw_best_per_read(sw_ctx *ctx, const sw_batch *batch, const sw_hit *d_h
 sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *batch, const sw_scoring *sc,
                              const uint32_t *d_pair_ids, uint32_t n_sel, sw_aln *d_aln,
                              uint32_t *d_ops, uint32_t ops_stride, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned candidate filter.
+ *
+ * The paper's stage D keeps a merged seed region as a candidate alignment
+ * location only when enough seed matches support it (Sec. 2, "Stage D: CAL
+ * Seeker"); stage E then runs Smith-Waterman on every candidate.  Here a
+ * small network scores each candidate window from its seed-hit features and
+ * Smith-Waterman runs only on the likely winners, with every candidate of a
+ * read kept whenever the network is unsure.
+ *
+ * Features: 64 bfloat16 values per pair (uint16_t storage), from the exact
+ * 12-mer matches of the read (first 256 query bases) in the window (first 4096
+ * bases): hit counts, diagonal concentration, position histograms, the same
+ * quantities relative to the read's other candidates, window length, GC and
+ * strand.  The pairs of one read must be contiguous in d_win and a read may
+ * have at most 64 candidates; other reads get no features and are always
+ * kept whole by sw_filter_candidates.
+ *
+ * Network: 64 -> 128 (ReLU) -> 128 (ReLU) -> 1 logit; bfloat16 operands on
+ * the matrix cores with float32 accumulation; float32 master parameters
+ * (SW_MLP_PARAMS values: W1[64][128], b1[128], W2[128][128], b2[128], w3[128],
+ * b3) trained with the mean binary cross-entropy on logits and Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8).
+ * ------------------------------------------------------------------------- */
+#define SW_FEATURES 64
+#define SW_MLP_PARAMS 24961
+
+typedef struct sw_mlp sw_mlp;
+
+typedef struct {
+    float logit_lo, logit_hi;   /* unsure band [lo, hi); keep logits >= hi */
+} sw_filter_params;
+
+sw_status sw_mlp_create(sw_ctx *ctx, sw_mlp **out);
+sw_status sw_mlp_destroy(sw_ctx *ctx, sw_mlp *mlp);
+/* Copy SW_MLP_PARAMS host floats into the network; resets the Adam state. */
+sw_status sw_mlp_set_params(sw_ctx *ctx, sw_mlp *mlp, const float *h_params);
+/* Copy the float32 master parameters to host memory (synchronous). */
+sw_status sw_mlp_get_params(sw_ctx *ctx, const sw_mlp *mlp, float *h_params);
+
+/* Features of every pair: d_feat[n_pairs * SW_FEATURES] (bfloat16 bits). */
+sw_status sw_features(sw_ctx *ctx, const sw_batch *batch, uint16_t *d_feat, void *stream);
+
+/* Logits of n feature rows (d_x[n * 64]) into d_logits[n]. */
+sw_status sw_mlp_forward(sw_ctx *ctx, const sw_mlp *mlp, const uint16_t *d_x, uint32_t n,
+                         float *d_logits, void *stream);
+
+/* Mean binary cross-entropy of n rows with labels d_y[n] (0 or 1) and its
+ * gradient (SW_MLP_PARAMS floats, parameter layout) without updating. */
+sw_status sw_mlp_grad(sw_ctx *ctx, const sw_mlp *mlp, const uint16_t *d_x, const float *d_y,
+                      uint32_t n, float *d_grad, float *d_loss, void *stream);
+
+/* One Adam step on the minibatch (d_x, d_y) with learning rate lr; d_loss
+ * (device float, may be NULL) receives the minibatch loss before the step. */
+sw_status sw_mlp_train_step(sw_ctx *ctx, sw_mlp *mlp, const uint16_t *d_x, const float *d_y,
+                            uint32_t n, float lr, float *d_loss, void *stream);
+
+/* Training labels from plain scores: d_y[p] = 1 if score(p) >= best score of
+ * its read - margin (d_best_score from sw_best_per_read), else 0. */
+sw_status sw_mlp_labels(sw_ctx *ctx, const sw_batch *batch, const sw_hit *d_hits,
+                        const int32_t *d_best_score, int32_t margin, float *d_y, void *stream);
+
+/* Filter step: features (into d_feat[n_pairs * 64]), logits (d_logits[n_pairs]),
+ * per-read decision (d_keep[n_pairs]: a read is unsure when its best logit is
+ * below logit_hi or any logit lies in [logit_lo, logit_hi); unsure reads keep
+ * every candidate, others keep the candidates with logit >= logit_hi) and
+ * stable compaction of the kept pairs into d_win_out / d_sel_ids (original
+ * pair index), with their number in *d_n_sel.  *d_n_unsure (device, may be
+ * NULL) is incremented by the number of unsure reads.  The kept list is ready
+ * for sw_batch_score through sw_batch.d_n_pairs. */
+sw_status sw_filter_candidates(sw_ctx *ctx, const sw_batch *batch, const sw_mlp *mlp,
+                               const sw_filter_params *fp, uint16_t *d_feat, float *d_logits,
+                               uint8_t *d_keep, sw_window *d_win_out, uint32_t *d_sel_ids,
+                               uint32_t *d_n_sel, uint32_t *d_n_unsure, void *stream);
 
 /* Context options (sw_ctx_set_option).
  * SW_OPT_INT16: 1 (default) lets score-only calls use the packed int16

@@ -52,7 +52,15 @@ class sw_batch(ctypes.Structure):
                 ("d_reads2b", ctypes.c_void_p), ("reads_len", ctypes.c_uint64),
                 ("d_read_off", ctypes.c_void_p), ("d_read_len", ctypes.c_void_p),
                 ("n_reads", ctypes.c_uint32), ("d_win", ctypes.c_void_p),
-                ("n_pairs", ctypes.c_uint32)]
+                ("n_pairs", ctypes.c_uint32), ("d_n_pairs", ctypes.c_void_p)]
+
+
+class sw_filter_params(ctypes.Structure):
+    _fields_ = [("logit_lo", ctypes.c_float), ("logit_hi", ctypes.c_float)]
+
+
+SW_FEATURES = 64
+SW_MLP_PARAMS = 24961
 
 
 _lib = None
@@ -80,9 +88,24 @@ def lib() -> ctypes.CDLL:
         L.sw_timing_enable.argtypes = [P, ctypes.c_int]
         L.sw_ctx_set_option.argtypes = [P, ctypes.c_int, ctypes.c_int]
         L.sw_timing_get.argtypes = [P, ctypes.POINTER(sw_timing)]
+        F = ctypes.c_float
+        L.sw_mlp_create.argtypes = [P, ctypes.POINTER(P)]
+        L.sw_mlp_destroy.argtypes = [P, P]
+        L.sw_mlp_set_params.argtypes = [P, P, P]
+        L.sw_mlp_get_params.argtypes = [P, P, P]
+        L.sw_features.argtypes = [P, ctypes.POINTER(sw_batch), P, P]
+        L.sw_mlp_forward.argtypes = [P, P, P, U32, P, P]
+        L.sw_mlp_grad.argtypes = [P, P, P, P, U32, P, P, P]
+        L.sw_mlp_train_step.argtypes = [P, P, P, P, U32, F, P, P]
+        L.sw_mlp_labels.argtypes = [P, ctypes.POINTER(sw_batch), P, P, I32, P, P]
+        L.sw_filter_candidates.argtypes = [P, ctypes.POINTER(sw_batch), P,
+                                           ctypes.POINTER(sw_filter_params), P, P, P, P, P, P, P, P]
         for f in ("sw_ctx_create", "sw_ctx_destroy", "sw_pack2b", "sw_batch_score",
                   "sw_best_per_read", "sw_batch_traceback", "sw_cigar_string",
-                  "sw_timing_enable", "sw_timing_get", "sw_ctx_set_option"):
+                  "sw_timing_enable", "sw_timing_get", "sw_ctx_set_option", "sw_mlp_create",
+                  "sw_mlp_destroy", "sw_mlp_set_params", "sw_mlp_get_params", "sw_features",
+                  "sw_mlp_forward", "sw_mlp_grad", "sw_mlp_train_step", "sw_mlp_labels",
+                  "sw_filter_candidates"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -153,6 +176,61 @@ def sw_timing_get(ctx) -> sw_timing:
     return t
 
 
+def sw_mlp_create(ctx):
+    h = ctypes.c_void_p()
+    _check(ctx, lib().sw_mlp_create(ctx, ctypes.byref(h)))
+    return h
+
+
+def sw_mlp_destroy(ctx, mlp):
+    _check(ctx, lib().sw_mlp_destroy(ctx, mlp))
+
+
+def sw_mlp_set_params(ctx, mlp, params: np.ndarray):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    assert a.size == SW_MLP_PARAMS
+    _check(ctx, lib().sw_mlp_set_params(ctx, mlp, a.ctypes.data_as(ctypes.c_void_p)))
+
+
+def sw_mlp_get_params(ctx, mlp) -> np.ndarray:
+    a = np.zeros(SW_MLP_PARAMS, dtype=np.float32)
+    _check(ctx, lib().sw_mlp_get_params(ctx, mlp, a.ctypes.data_as(ctypes.c_void_p)))
+    return a
+
+
+def sw_features(ctx, batch, d_feat, stream=None):
+    _check(ctx, lib().sw_features(ctx, ctypes.byref(batch.c), _ptr(d_feat), _stream_ptr(stream)))
+
+
+def sw_mlp_forward(ctx, mlp, d_x, n, d_logits, stream=None):
+    _check(ctx, lib().sw_mlp_forward(ctx, mlp, _ptr(d_x), int(n), _ptr(d_logits),
+                                     _stream_ptr(stream)))
+
+
+def sw_mlp_grad(ctx, mlp, d_x, d_y, n, d_grad, d_loss, stream=None):
+    _check(ctx, lib().sw_mlp_grad(ctx, mlp, _ptr(d_x), _ptr(d_y), int(n), _ptr(d_grad),
+                                  _ptr(d_loss), _stream_ptr(stream)))
+
+
+def sw_mlp_train_step(ctx, mlp, d_x, d_y, n, lr, d_loss=None, stream=None):
+    _check(ctx, lib().sw_mlp_train_step(ctx, mlp, _ptr(d_x), _ptr(d_y), int(n), float(lr),
+                                        _ptr(d_loss), _stream_ptr(stream)))
+
+
+def sw_mlp_labels(ctx, batch, d_hits, d_best_score, margin, d_y, stream=None):
+    _check(ctx, lib().sw_mlp_labels(ctx, ctypes.byref(batch.c), _ptr(d_hits), _ptr(d_best_score),
+                                    int(margin), _ptr(d_y), _stream_ptr(stream)))
+
+
+def sw_filter_candidates(ctx, batch, mlp, logit_lo, logit_hi, d_feat, d_logits, d_keep,
+                         d_win_out, d_sel_ids, d_n_sel, d_n_unsure=None, stream=None):
+    fp = sw_filter_params(float(logit_lo), float(logit_hi))
+    _check(ctx, lib().sw_filter_candidates(ctx, ctypes.byref(batch.c), mlp, ctypes.byref(fp),
+                                           _ptr(d_feat), _ptr(d_logits), _ptr(d_keep),
+                                           _ptr(d_win_out), _ptr(d_sel_ids), _ptr(d_n_sel),
+                                           _ptr(d_n_unsure), _stream_ptr(stream)))
+
+
 def sw_cigar_string(ops) -> str:
     a = np.ascontiguousarray(ops, dtype=np.uint32)
     buf = ctypes.create_string_buffer(16 * len(a) + 1)
@@ -203,7 +281,19 @@ class DeviceBatch:
         self.pack_reads(stream)
         self.c = sw_batch(_ptr(self.ref2b), self.ref_len, _ptr(self.reads2b), self.reads_len,
                           _ptr(self.read_off), _ptr(self.read_len), self.n_reads, _ptr(self.win),
-                          self.n_pairs)
+                          self.n_pairs, None)
+
+    def view(self, win, n_pairs, d_n_pairs=None):
+        """The same reads and reference with another window list (e.g. a
+        compacted work list whose count stays on the device)."""
+        v = object.__new__(DeviceBatch)
+        v.__dict__.update(self.__dict__)
+        v.win_view = win
+        v.n_pairs = n_pairs
+        v.c = sw_batch(_ptr(self.ref2b), self.ref_len, _ptr(self.reads2b), self.reads_len,
+                       _ptr(self.read_off), _ptr(self.read_len), self.n_reads, _ptr(win),
+                       n_pairs, _ptr(d_n_pairs))
+        return v
 
     def pack_reads(self, stream=None):
         """Encode step for the reads (ASCII already in device memory)."""

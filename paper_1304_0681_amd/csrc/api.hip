@@ -7,6 +7,7 @@
 #include <string>
 
 #include "internal.h"
+#include "mlp_internal.h"
 
 namespace hpgsw {
 
@@ -40,6 +41,9 @@ struct sw_ctx {
     uint32_t *tb = nullptr;
     size_t tb_bytes = 0;
     uint32_t *host_meta = nullptr;   // pinned: per-class segments and maxima
+    // filter scratch: read segments (first, last, count) and compaction offsets
+    uint32_t *seg = nullptr;
+    size_t seg_bytes = 0;
     ClassShape shapes[kNumClasses];
     int blocks_per_cu[kNumClasses];
     bool int16 = true;   // packed int16 datapath where exact
@@ -193,6 +197,7 @@ sw_status sw_ctx_destroy(sw_ctx *ctx)
     if (ctx->strip_buf) keep(hipFree(ctx->strip_buf));
     if (ctx->keys) keep(hipFree(ctx->keys));
     if (ctx->tb) keep(hipFree(ctx->tb));
+    if (ctx->seg) keep(hipFree(ctx->seg));
     if (ctx->host_meta) keep(hipHostFree(ctx->host_meta));
     for (auto &ev : ctx->ev)
         if (ev) keep(hipEventDestroy(ev));
@@ -438,6 +443,258 @@ sw_status sw_timing_get(sw_ctx *ctx, sw_timing *out)
         out->score_ms += out->class_ms[c];
         out->class_path[c] = ctx->class_path[c];
     }
+    return SW_OK;
+}
+
+}  // extern "C"
+
+struct sw_mlp {
+    float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *loss = nullptr;
+    uint16_t *bf = nullptr;     // w1t | w2t | w2 | w3b
+    int step = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    MlpDev dev() const
+    {
+        MlpDev d;
+        d.w1t = bf;
+        d.w2t = bf + kIn * kHidden;
+        d.w2 = d.w2t + kHidden * kHidden;
+        d.w3b = d.w2 + kHidden * kHidden;
+        d.b1 = theta + kOffB1;
+        d.b2 = theta + kOffB2;
+        d.b3 = theta + kOffB3;
+        return d;
+    }
+};
+
+namespace {
+
+sw_status mlp_workspace(sw_ctx *ctx, sw_mlp *mlp, uint32_t n)
+{
+    return ensure(ctx, &mlp->ws, &mlp->ws_bytes, mlp_workspace_bytes(n));
+}
+
+sw_status filter_scratch(sw_ctx *ctx, uint32_t n_reads, uint32_t n_pairs, uint32_t **first,
+                         uint32_t **last, uint32_t **count, uint32_t **cscan)
+{
+    const size_t nr = align_up(4ull * std::max<uint32_t>(n_reads, 1));
+    const size_t need = 3 * nr + align_up(4 * compact_scratch_words(n_pairs));
+    void *buf = ctx->seg;
+    size_t have = ctx->seg_bytes;
+    sw_status st = ensure(ctx, &buf, &have, need);
+    if (st)
+        return st;
+    ctx->seg = static_cast<uint32_t *>(buf);
+    ctx->seg_bytes = have;
+    char *p = static_cast<char *>(buf);
+    *first = reinterpret_cast<uint32_t *>(p);
+    *last = reinterpret_cast<uint32_t *>(p + nr);
+    *count = reinterpret_cast<uint32_t *>(p + 2 * nr);
+    *cscan = reinterpret_cast<uint32_t *>(p + 3 * nr);
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sw_status sw_mlp_create(sw_ctx *ctx, sw_mlp **out)
+{
+    if (!ctx || !out)
+        return fail(ctx, SW_E_INVALID, "NULL argument");
+    *out = nullptr;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    sw_mlp *m = new sw_mlp;
+    const size_t fb = align_up(4ull * kParams);
+    const size_t bb = 2ull * (kIn * kHidden + 2 * kHidden * kHidden + kHidden);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, 4 * fb + 256 + align_up(bb));
+    if (e != hipSuccess) {
+        delete m;
+        return fail(ctx, SW_E_NOMEM, "sw_mlp_create: %s", hipGetErrorString(e));
+    }
+    char *c = static_cast<char *>(p);
+    m->theta = reinterpret_cast<float *>(c);
+    m->m = reinterpret_cast<float *>(c + fb);
+    m->v = reinterpret_cast<float *>(c + 2 * fb);
+    m->grad = reinterpret_cast<float *>(c + 3 * fb);
+    m->loss = reinterpret_cast<float *>(c + 4 * fb);
+    m->bf = reinterpret_cast<uint16_t *>(c + 4 * fb + 256);
+    e = hipMemset(p, 0, 4 * fb + 256 + align_up(bb));
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        delete m;
+        return fail(ctx, SW_E_DEVICE, "sw_mlp_create: %s", hipGetErrorString(e));
+    }
+    *out = m;
+    return SW_OK;
+}
+
+sw_status sw_mlp_destroy(sw_ctx *ctx, sw_mlp *mlp)
+{
+    if (!mlp)
+        return fail(ctx, SW_E_INVALID, "mlp is NULL");
+    hipError_t e = hipDeviceSynchronize();
+    if (mlp->theta && e == hipSuccess)
+        e = hipFree(mlp->theta);
+    if (mlp->ws && e == hipSuccess)
+        e = hipFree(mlp->ws);
+    delete mlp;
+    if (e != hipSuccess)
+        return fail(ctx, SW_E_DEVICE, "sw_mlp_destroy: %s", hipGetErrorString(e));
+    return SW_OK;
+}
+
+sw_status sw_mlp_set_params(sw_ctx *ctx, sw_mlp *mlp, const float *h_params)
+{
+    if (!ctx || !mlp || !h_params)
+        return fail(ctx, SW_E_INVALID, "NULL argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipMemcpy(mlp->theta, h_params, 4ull * kParams, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemset(mlp->m, 0, 4ull * kParams));
+    HIP_TRY(ctx, hipMemset(mlp->v, 0, 4ull * kParams));
+    mlp->step = 0;
+    HIP_TRY(ctx, mlp_cast_params(mlp->theta, mlp->dev(), nullptr));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    return SW_OK;
+}
+
+sw_status sw_mlp_get_params(sw_ctx *ctx, const sw_mlp *mlp, float *h_params)
+{
+    if (!ctx || !mlp || !h_params)
+        return fail(ctx, SW_E_INVALID, "NULL argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    HIP_TRY(ctx, hipMemcpy(h_params, mlp->theta, 4ull * kParams, hipMemcpyDeviceToHost));
+    return SW_OK;
+}
+
+sw_status sw_features(sw_ctx *ctx, const sw_batch *b, uint16_t *d_feat, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    sw_status st = check_batch(ctx, b);
+    if (st)
+        return st;
+    if (b->n_pairs == 0)
+        return SW_OK;
+    if (!d_feat)
+        return fail(ctx, SW_E_INVALID, "d_feat is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    uint32_t *first, *last, *count, *cscan;
+    if ((st = filter_scratch(ctx, b->n_reads, b->n_pairs, &first, &last, &count, &cscan)))
+        return st;
+    HIP_TRY(ctx, read_segments(b->n_pairs, b->d_n_pairs, b->d_win, b->n_reads, first, last, count, s));
+    HIP_TRY(ctx, launch_features(*b, first, count, d_feat, ctx->n_cu, s));
+    return SW_OK;
+}
+
+sw_status sw_mlp_forward(sw_ctx *ctx, const sw_mlp *mlp, const uint16_t *d_x, uint32_t n,
+                         float *d_logits, void *stream)
+{
+    if (!ctx || !mlp)
+        return fail(ctx, SW_E_INVALID, "NULL argument");
+    if (n == 0)
+        return SW_OK;
+    if (!d_x || !d_logits)
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, mlp_infer(mlp->dev(), d_x, n, nullptr, d_logits, ctx->n_cu,
+                           static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_mlp_grad(sw_ctx *ctx, const sw_mlp *mlp, const uint16_t *d_x, const float *d_y,
+                      uint32_t n, float *d_grad, float *d_loss, void *stream)
+{
+    if (!ctx || !mlp || !d_x || !d_y || !d_grad || !d_loss)
+        return fail(ctx, SW_E_INVALID, "NULL argument");
+    if (n == 0 || n > (1u << 20))
+        return fail(ctx, SW_E_RANGE, "minibatch must hold 1..2^20 rows");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    sw_mlp *mm = const_cast<sw_mlp *>(mlp);
+    sw_status st = mlp_workspace(ctx, mm, n);
+    if (st)
+        return st;
+    HIP_TRY(ctx, mlp_backprop(mlp->dev(), d_x, d_y, n, d_grad, d_loss, mm->ws,
+                              static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_mlp_train_step(sw_ctx *ctx, sw_mlp *mlp, const uint16_t *d_x, const float *d_y,
+                            uint32_t n, float lr, float *d_loss, void *stream)
+{
+    if (!ctx || !mlp || !d_x || !d_y)
+        return fail(ctx, SW_E_INVALID, "NULL argument");
+    if (n == 0 || n > (1u << 20))
+        return fail(ctx, SW_E_RANGE, "minibatch must hold 1..2^20 rows");
+    if (!(lr > 0.f))
+        return fail(ctx, SW_E_INVALID, "learning rate must be positive");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    sw_status st = mlp_workspace(ctx, mlp, n);
+    if (st)
+        return st;
+    HIP_TRY(ctx, mlp_backprop(mlp->dev(), d_x, d_y, n, mlp->grad, d_loss ? d_loss : mlp->loss,
+                              mlp->ws, s));
+    mlp->step += 1;
+    HIP_TRY(ctx, mlp_adam(mlp->theta, mlp->m, mlp->v, mlp->grad, lr, mlp->step, s));
+    HIP_TRY(ctx, mlp_cast_params(mlp->theta, mlp->dev(), s));
+    return SW_OK;
+}
+
+sw_status sw_mlp_labels(sw_ctx *ctx, const sw_batch *b, const sw_hit *d_hits,
+                        const int32_t *d_best_score, int32_t margin, float *d_y, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    sw_status st = check_batch(ctx, b);
+    if (st)
+        return st;
+    if (b->n_pairs == 0)
+        return SW_OK;
+    if (!d_hits || !d_best_score || !d_y)
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, mlp_labels(b->n_pairs, b->d_win, d_hits, d_best_score, margin, d_y,
+                            static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_filter_candidates(sw_ctx *ctx, const sw_batch *b, const sw_mlp *mlp,
+                               const sw_filter_params *fp, uint16_t *d_feat, float *d_logits,
+                               uint8_t *d_keep, sw_window *d_win_out, uint32_t *d_sel_ids,
+                               uint32_t *d_n_sel, uint32_t *d_n_unsure, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    sw_status st = check_batch(ctx, b);
+    if (st)
+        return st;
+    if (!mlp || !fp || !d_n_sel)
+        return fail(ctx, SW_E_INVALID, "NULL argument");
+    if (!(fp->logit_lo <= fp->logit_hi))
+        return fail(ctx, SW_E_INVALID, "logit_lo must not exceed logit_hi");
+    if (b->d_n_pairs)
+        return fail(ctx, SW_E_INVALID, "the filter takes a batch with a host pair count");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (b->n_pairs == 0)
+        return SW_OK;
+    if (!d_feat || !d_logits || !d_keep || !d_win_out || !d_sel_ids)
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    uint32_t *first, *last, *count, *cscan;
+    if ((st = filter_scratch(ctx, b->n_reads, b->n_pairs, &first, &last, &count, &cscan)))
+        return st;
+    HIP_TRY(ctx, read_segments(b->n_pairs, nullptr, b->d_win, b->n_reads, first, last, count, s));
+    HIP_TRY(ctx, launch_features(*b, first, count, d_feat, ctx->n_cu, s));
+    HIP_TRY(ctx, mlp_infer(mlp->dev(), d_feat, b->n_pairs, nullptr, d_logits, ctx->n_cu, s));
+    uint32_t *unsure = d_n_unsure ? d_n_unsure : cscan + compact_scratch_words(b->n_pairs) - 1;
+    HIP_TRY(ctx, filter_decide(b->n_pairs, b->d_win, b->n_reads, first, last, count, d_logits,
+                               fp->logit_lo, fp->logit_hi, d_keep, unsure, s));
+    HIP_TRY(ctx, compact_pairs(b->n_pairs, d_keep, b->d_win, d_win_out, d_sel_ids, d_n_sel, cscan, s));
     return SW_OK;
 }
 

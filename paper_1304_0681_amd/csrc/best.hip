@@ -15,10 +15,12 @@ __global__ void __launch_bounds__(256) k_best_init(uint32_t n_reads, uint64_t *k
         keys[r] = 0;
 }
 
-__global__ void __launch_bounds__(256) k_best_update(uint32_t n_pairs, const sw_window *win,
-                                                     const sw_hit *hits, uint32_t n_reads,
-                                                     uint64_t *keys)
+__global__ void __launch_bounds__(256) k_best_update(uint32_t n_pairs, const uint32_t *d_n,
+                                                     const sw_window *win, const sw_hit *hits,
+                                                     uint32_t n_reads, uint64_t *keys)
 {
+    if (d_n)
+        n_pairs = min(n_pairs, *d_n);
     for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < n_pairs;
          p += (uint64_t)gridDim.x * 256) {
         const int s = hits[p].score;
@@ -62,7 +64,7 @@ hipError_t launch_best(const sw_batch &b, const sw_hit *hits, uint64_t *keys, in
     hipLaunchKernelGGL(k_best_init, dim3(grid_for(b.n_reads)), dim3(256), 0, st, b.n_reads, keys);
     if (b.n_pairs)
         hipLaunchKernelGGL(k_best_update, dim3(grid_for(b.n_pairs)), dim3(256), 0, st, b.n_pairs,
-                           b.d_win, hits, b.n_reads, keys);
+                           b.d_n_pairs, b.d_win, hits, b.n_reads, keys);
     hipLaunchKernelGGL(k_best_final, dim3(grid_for(b.n_reads)), dim3(256), 0, st, b.n_reads, keys,
                        t_map, best_pair, best_score, mapped);
     return hipGetLastError();

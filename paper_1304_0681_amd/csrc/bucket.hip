@@ -103,6 +103,8 @@ __global__ void __launch_bounds__(kBlock) k_classify(sw_batch b, const uint32_t 
     if (threadIdx.x < 2 * kNumClasses)
         lmax[threadIdx.x] = 0;
     __syncthreads();
+    if (!sel && b.d_n_pairs)
+        n_items = min(n_items, *b.d_n_pairs);
     const uint64_t base = (uint64_t)blockIdx.x * kBlock * kItems;
     for (int k = 0; k < kItems; ++k) {
         const uint64_t p = base + (uint64_t)k * kBlock + threadIdx.x;
@@ -165,9 +167,12 @@ __global__ void __launch_bounds__(1024) k_scan(uint32_t *hist, uint32_t *seg, ui
         counter[t] = 0;
 }
 
-__global__ void __launch_bounds__(kBlock) k_scatter(uint32_t n_pairs, const uint32_t *bin_in,
-                                                    uint32_t *cursor, uint32_t *ids)
+__global__ void __launch_bounds__(kBlock) k_scatter(uint32_t n_pairs, const uint32_t *d_n,
+                                                    const uint32_t *bin_in, uint32_t *cursor,
+                                                    uint32_t *ids)
 {
+    if (d_n)
+        n_pairs = min(n_pairs, *d_n);
     __shared__ uint32_t lh[kNumBins];
     for (int i = threadIdx.x; i < kNumBins; i += kBlock)
         lh[i] = 0;
@@ -208,8 +213,8 @@ hipError_t launch_bucket(const sw_batch &b, const uint32_t *sel, uint32_t n_item
                            s.hist, s.maxlen, hits, aln);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, s.hist, s.seg, s.counter);
     if (n_items)
-        hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(kBlock), 0, st, n_items, s.bin, s.hist,
-                           s.ids);
+        hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(kBlock), 0, st, n_items,
+                           sel ? nullptr : b.d_n_pairs, s.bin, s.hist, s.ids);
     return hipGetLastError();
 }
 

@@ -1,0 +1,39 @@
+"""Host logic of the filter: the decision rule and threshold calibration."""
+import numpy as np
+
+from paper_1304_0681_amd import train as tr
+
+
+def test_decision_rule_and_recall():
+    rid = np.array([0, 0, 0, 1, 1, 2, 2, 2])
+    z = np.array([5.0, -3.0, -4.0, 0.5, -2.0, 4.0, 1.0, -5.0])
+    scores = np.array([90, 10, 20, 30, 40, 70, 70, 5])
+    best = np.array([90, 40, 70])
+    keep, hit, unsure = tr.filter_outcome(z, scores, best, rid, lo=0.0, hi=2.0)
+    # read 0: sure (max 5 >= 2, nothing in [0, 2)) -> keeps only pair 0, the best
+    # read 1: max 0.5 < 2 -> unsure -> keeps both
+    # read 2: z = 1.0 in [0, 2) -> unsure -> keeps all three
+    assert keep.tolist() == [True, False, False, True, True, True, True, True]
+    assert unsure.tolist() == [False, True, True]
+    assert hit.all()
+    keep, hit, _ = tr.filter_outcome(z, scores, best, rid, lo=1.5, hi=1.5)
+    assert keep.tolist() == [True, False, False, True, True, True, False, False]
+    assert hit.tolist() == [True, True, True]      # pair 5 (score 70) is a best pair
+
+
+def test_calibration_meets_target():
+    g = np.random.default_rng(0)
+    n_reads, K = 3000, 16
+    rid = np.repeat(np.arange(n_reads), K)
+    scores = g.integers(20, 60, n_reads * K)
+    true = g.integers(0, K, n_reads)
+    has = g.random(n_reads) < 0.8
+    idx = np.arange(n_reads) * K + true
+    scores[idx[has]] = 480
+    best = np.maximum.reduceat(scores, np.arange(n_reads) * K)
+    z = g.normal(-4, 1, n_reads * K)
+    z[idx[has]] = g.normal(4, 1, has.sum())
+    lo, hi, rec = tr.calibrate(z, scores, best, rid, target=0.999)
+    keep, hit, _ = tr.filter_outcome(z, scores, best, rid, lo, hi)
+    assert hit.mean() >= 0.999 and rec == hit.mean()
+    assert keep.mean() < 0.5
