@@ -12,6 +12,15 @@ read.
 Prints one JSON line with GCUPS (the value), reads/s, the roofline of the
 dominant kernel (timed with HIP events inside the timed region) and the CPU
 oracle timed on a bounded sample of the same workload.
+
+The "filter" object compares plain and learned-filter forms on the
+learned-filter workload: 1,000,000 reads of 100 nt, exactly 16 candidate
+windows each (16 M pairs).  The network is trained on the GPU (library
+kernels) on labels from plain SW over a separate 200,000-read set, its
+thresholds are calibrated on a third set, and both forms are then timed on the
+test set: one filtered step = encode, features, MLP, per-read decision,
+compaction, SW on the kept pairs (every candidate of unsure reads) and best
+hit per read.  Recall = reads whose filtered best score equals the plain one.
 """
 from __future__ import annotations
 
@@ -73,6 +82,110 @@ def cpu_baseline(batch, target_s: float):
     }
 
 
+def bench_filter(ctx, args):
+    """Plain vs learned filter on the 16-candidate workload (see module doc)."""
+    import torch
+
+    import paper_1304_0681_amd as sw
+    import synth
+    from paper_1304_0681_amd import train as tr
+
+    t0 = time.perf_counter()
+    # training data: labels from plain SW on a separate seed
+    b_tr = synth.config4(n_reads=200_000, seed=synth.BASE_SEED + 14)
+    db_tr = sw.DeviceBatch.from_synth(ctx, b_tr)
+    p_tr = tr.plain_scores(ctx, db_tr)
+    feat, y = tr.features_and_labels(ctx, db_tr, p_tr)
+    pos_frac = float(y.mean().item())
+    t1 = time.perf_counter()
+    mlp, losses = tr.train(ctx, feat, y, steps=args.train_steps, batch=4096, seed=1,
+                           log_every=max(args.train_steps // 5, 1))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    del feat, y, p_tr, db_tr
+    # calibration on a second seed
+    b_ca = synth.config4(n_reads=200_000, seed=synth.BASE_SEED + 24)
+    db_ca = sw.DeviceBatch.from_synth(ctx, b_ca)
+    p_ca = tr.plain_scores(ctx, db_ca)
+    f_ca, _ = tr.features_and_labels(ctx, db_ca, p_ca)
+    z = tr.logits_of(ctx, mlp, f_ca).cpu().numpy()
+    lo, hi, rec_cal = tr.calibrate(z, p_ca.hits[:, 0].cpu().numpy(), p_ca.best_score.cpu().numpy(),
+                                   b_ca.windows["read_id"].astype(np.int64), target=0.9995)
+    del f_ca, p_ca, db_ca
+    log(f"filter: trained {args.train_steps} steps in {t_train:.1f} s "
+        f"(loss {losses[0][1]:.4f} -> {losses[-1][1]:.4f}), thresholds [{lo:.3f}, {hi:.3f}), "
+        f"calibration recall {rec_cal:.5f}")
+    # test set
+    b = synth.config4(n_reads=args.filter_reads)
+    cells_all = b.cells()
+    db = sw.DeviceBatch.from_synth(ctx, b)
+    hits = torch.empty((b.n_pairs, 3), dtype=torch.int32, device="cuda")
+    bp = torch.empty(b.n_reads, dtype=torch.int32, device="cuda")
+    bs = torch.empty(b.n_reads, dtype=torch.int32, device="cuda")
+    buf = tr.FilterBuffers(b.n_pairs, b.n_reads)
+
+    def plain_step():
+        db.pack_reads()
+        sw.sw_batch_score(ctx, db, SCORING, 0, hits)
+        sw.sw_best_per_read(ctx, db, hits, 0, bp, bs)
+
+    def filt_step():
+        db.pack_reads()
+        tr.filtered_pass(ctx, mlp, db, lo, hi, buf)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / args.steps
+
+    sw.sw_timing_enable(ctx, False)
+    t_plain = timed(plain_step)
+    plain_best = bs.cpu().numpy()
+    plain_scores = hits[:, 0].cpu().numpy()
+    t_filt = timed(filt_step)
+    filt_best = buf.best_score.cpu().numpy()
+    keep = buf.keep.cpu().numpy().astype(bool)
+    n_unsure = int(buf.n_unsure.item())
+    rid = b.windows["read_id"].astype(np.int64)
+    m = b.read_len[rid].astype(np.int64)
+    n = np.minimum(b.windows["len"].astype(np.int64),
+                   len(b.ref) - b.windows["ref_begin"].astype(np.int64))
+    cells_kept = int((m * n)[keep].sum())
+    recall = float((filt_best == plain_best).mean())
+    mappable = plain_best >= 250
+    recall_map = float((filt_best[mappable] == plain_best[mappable]).mean())
+    # also check that every filtered best score is a plain score of a kept pair
+    assert (filt_best <= plain_best).all()
+    sw.sw_mlp_destroy(ctx, mlp)
+    return {
+        "workload": "learned-filter: 1M x 100-nt reads vs exactly 16 windows of 200-600 nt "
+                    "(4 Mb GC-40% reference), scores only",
+        "reads": b.n_reads, "pairs": b.n_pairs,
+        "plain": {"ms_per_step": round(t_plain * 1e3, 3),
+                  "reads_per_s": round(b.n_reads / t_plain, 1),
+                  "gcups": round(cells_all / t_plain / 1e9, 1)},
+        "filtered": {"ms_per_step": round(t_filt * 1e3, 3),
+                     "reads_per_s": round(b.n_reads / t_filt, 1),
+                     "gcups_effective": round(cells_all / t_filt / 1e9, 1),
+                     "gcups_dp": round(cells_kept / t_filt / 1e9, 1),
+                     "kept_pairs_fraction": round(float(keep.mean()), 5),
+                     "unsure_reads_fraction": round(n_unsure / b.n_reads, 5)},
+        "speedup_reads_per_s": round(t_plain / t_filt, 3),
+        "best_hit_recall": recall,
+        "best_hit_recall_mappable": recall_map,
+        "thresholds": [lo, hi], "calibration_recall": rec_cal,
+        "train": {"reads": 200_000, "pairs": 3_200_000, "steps": args.train_steps,
+                  "batch": 4096, "seconds": round(t_train, 2), "positive_fraction": round(pos_frac, 4),
+                  "loss": [[s_, round(l_, 5)] for s_, l_ in losses]},
+        "setup_seconds": round(time.perf_counter() - t0, 1),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +196,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--no-filter", action="store_true", help="skip the learned-filter comparison")
+    ap.add_argument("--filter-reads", type=int, default=1_000_000)
+    ap.add_argument("--train-steps", type=int, default=1500)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -183,6 +299,9 @@ def main():
             "frac_of_int32_roofline": round(kern_gcups / PEAK_GCUPS_INT32, 4),
         },
     }
+    if not args.no_filter:
+        del db, hits
+        out["filter"] = bench_filter(ctx, args)
     sw.sw_ctx_destroy(ctx)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

@@ -174,7 +174,7 @@ sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *batch, const sw_scorin
  * read kept whenever the network is unsure.
  *
  * Features: 64 bfloat16 values per pair (uint16_t storage), from the exact
- * 12-mer matches of the read (first 256 query bases) in the window (first 4096
+ * 12-mer matches of the read (first 256 query bases) in the window (first 1024
  * bases): hit counts, diagonal concentration, position histograms, the same
  * quantities relative to the read's other candidates, window length, GC and
  * strand.  The pairs of one read must be contiguous in d_win and a read may

@@ -9,7 +9,7 @@ plain definition of those 64 features, written directly from it:
   query q   the read, or its reverse complement for a strand-1 window, cut to
             its first MF = 256 bases; m = len(q)
   window t  the reference window clipped to the reference, cut to its first
-            NF = 4096 bases; n = len(t)
+            NF = 1024 bases; n = len(t)
   k-mers    every k = 12 base substring, q at p = 0..P-1 (P = m-k+1), t at
             j = 0..J-1 (J = n-k+1)
   hits      all (p, j) with q[p:p+k] == t[j:j+k]; diagonal d = j - p, bin
@@ -43,7 +43,7 @@ import numpy as np
 
 K = 12
 MF = 256
-NF = 4096
+NF = 1024
 NFEAT = 64
 
 

@@ -356,9 +356,11 @@ __global__ void __launch_bounds__(256) k_seg_init(uint32_t n_reads, uint32_t *fi
     }
 }
 
+// Runs of equal read ids: a read's first pair (min over its run starts), last
+// pair (max over run ends) and number of runs; atomics only at run boundaries.
 __global__ void __launch_bounds__(256) k_seg(uint32_t n_pairs, const uint32_t *d_n, const sw_window *win,
                                              uint32_t n_reads, uint32_t *first, uint32_t *last,
-                                             uint32_t *count)
+                                             uint32_t *runs)
 {
     const uint32_t p = blockIdx.x * 256 + threadIdx.x;
     if (d_n)
@@ -368,9 +370,24 @@ __global__ void __launch_bounds__(256) k_seg(uint32_t n_pairs, const uint32_t *d
     const uint32_t r = win[p].read_id;
     if (r >= n_reads)
         return;
-    atomicMin(first + r, p);
-    atomicMax(last + r, p);
-    atomicAdd(count + r, 1u);
+    if (p == 0 || win[p - 1].read_id != r) {
+        atomicMin(first + r, p);
+        atomicAdd(runs + r, 1u);
+    }
+    if (p + 1 == n_pairs || win[p + 1].read_id != r)
+        atomicMax(last + r, p);
+}
+
+// count = pairs of a read stored in one run; a read split over several runs gets
+// 0xFFFFFFFF, which fails every contiguity test (its pairs are all kept)
+__global__ void __launch_bounds__(256) k_seg_final(uint32_t n_reads, const uint32_t *first,
+                                                   const uint32_t *last, uint32_t *count)
+{
+    const uint32_t r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= n_reads)
+        return;
+    const uint32_t runs = count[r];
+    count[r] = runs == 0 ? 0u : (runs == 1 ? last[r] - first[r] + 1 : 0xFFFFFFFFu);
 }
 
 // Per read: keep all candidates when unsure (best logit below hi, or any
@@ -640,6 +657,7 @@ hipError_t read_segments(uint32_t n_pairs, const uint32_t *d_n, const sw_window 
     if (n_pairs)
         hipLaunchKernelGGL(k_seg, dim3(blocks_for(n_pairs)), dim3(256), 0, st, n_pairs, d_n, win,
                            n_reads, first, last, count);
+    hipLaunchKernelGGL(k_seg_final, dim3(blocks_for(n_reads)), dim3(256), 0, st, n_reads, first, last, count);
     return hipGetLastError();
 }
 
