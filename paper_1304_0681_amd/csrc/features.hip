@@ -7,17 +7,19 @@
 //
 // One wave per read.  The read's 12-mers, for both orientations, go into two
 // open-addressing hash tables in LDS (at most 245 k-mers in 512 slots each),
-// each with an 8192-bit prefilter bitmap.  The wave then takes the read's
-// candidate windows four at a time, 16 lanes per window.  A lane owns whole
-// 16-base words of the reference: it loads a word and its successor once and
-// forms the 16 k-mers that start in the word with funnel shifts, so the 16
-// bitmap reads of a word issue back to back and only bitmap hits (true seed
-// matches plus about 3 % false positives) probe the table.  Every hit (p, j)
-// goes into LDS accumulators (diagonal bins of width 16, a bitmap of hit read
-// positions, two 16-bin position histograms).  When a window is done its 16
-// lanes write the per-candidate features (four each); a last pass adds the
-// features that compare the read's candidates.  Features are computed in
-// float32 and rounded to bfloat16.
+// each with an 8192-bit prefilter bitmap indexed by the k-mer's first 6.5
+// bases.  The wave then takes the read's candidate windows sixteen at a time
+// and treats their reference words (16 bases each) as one flat stream: lane l
+// of a 64-word chunk owns word l of the stream, whatever window it belongs to,
+// so no lane idles at a window's end.  A lane forms the 16 k-mers that start in
+// its word with shifts of the word pair, tests all 16 against the bitmap (five
+// VALU operations each) and probes the table only for bitmap hits (true seed
+// matches plus about 3 % false positives).  Every hit (p, j) goes into the
+// window's LDS row: diagonal-bin counters (two 16-bit halves per word), a
+// bitmap of hit read positions and two 16-bin position histograms.  When the
+// group is done, four lanes per window reduce the row to the statistics, and
+// the wave writes one 128-byte feature row per window (lane f: feature f).
+// Features are computed in float32 and rounded to bfloat16.
 #include "mlp_internal.h"
 
 namespace hpgsw {
@@ -29,20 +31,36 @@ constexpr int kMF = 256;           // query bases used
 constexpr int kNF = 1024;          // window bases used
 constexpr int kTab = 512;          // hash slots per orientation
 constexpr int kBm = 256;           // prefilter bitmap words per orientation (8192 bits)
-constexpr int kSlots = 4;          // candidates in flight per wave
-constexpr int kMaxBins = (kNF + kMF) / 16 + 3;
-constexpr int kWavesF = 4;         // waves per block
-constexpr uint32_t kGold = 0x9E3779B1u;
+constexpr int kG = 16;             // windows per group
+constexpr int kWavesF = 2;         // waves per block
+constexpr uint32_t kGold24 = 0x9E3779u;   // odd 24-bit multiplier of the table hash
+
+// Row of one window (32-bit words).  Words 0..63 are its feature row: for the
+// features divided by max(P, 1) a word holds the integer numerator, for the
+// others the finished bfloat16 pattern.  Words 7..38 (the position
+// histograms) are accumulated in place.
+constexpr int kRowBins = 64;       // 42 words: diagonal-bin counters, 16 bits each
+constexpr int kRowPbits = 106;     // 8 words: bitmap of hit read positions
+constexpr int kRowGc = 114;        // G+C count of the window
+constexpr int kRow = 116;
+// features whose value is (integer numerator) / max(P, 1): 0..3, 7..40, 43
+constexpr uint64_t kOverP = 0xFull | (((1ull << 34) - 1) << 7) | (1ull << 43);
+
+static_assert((kNF + kMF) / 32 + 2 <= kRowPbits - kRowBins, "diagonal bins do not fit the row");
 
 struct alignas(16) WaveLds {
-    uint32_t key[2][kTab];
-    uint32_t bm[2][kBm];
-    uint16_t pos[2][kTab];
-    uint32_t bins[kSlots][kMaxBins];
-    uint32_t pbits[kSlots][kMF / 32];
-    uint32_t acc[kSlots][36];      // nh, gc, hist_p[16], hist_j[16], (2 spare)
+    uint32_t tab[2][kTab];         // (k-mer << 8) | read position, 0xFFFFFFFF = empty
+    uint32_t acc[kG][kRow];
+    uint16_t lut[256];             // bfloat16 of x / max(P, 1)
+    uint32_t rd[kMF / 16 + 2];     // packed words holding the read's first 256 bases
+    uint32_t rr[kMF / 16 + 2];     // packed words holding its last 256 bases
+    uint32_t wrb[kMaxCand];        // window start
+    uint16_t wnf[kMaxCand];        // window bases used
+    uint8_t wst[kMaxCand];         // strand
     uint32_t nm3[kMaxCand];
     uint32_t ndp[kMaxCand];
+    uint32_t cwo[kG + 1];          // first stream word of each window of the group
+    float rj[kG];                  // 16 / max(J, 1)
 };
 
 __device__ __forceinline__ uint16_t f2bf(float x)
@@ -52,19 +70,25 @@ __device__ __forceinline__ uint16_t f2bf(float x)
     return (uint16_t)(u >> 16);
 }
 
-// 12-mer starting at base position `pos` of a packed sequence of `words` words
-__device__ __forceinline__ uint32_t kmer_at(const uint32_t *seq, uint64_t words, uint64_t pos)
-{
-    const uint64_t w0 = pos >> 4;
-    const uint64_t w1 = w0 + 1 < words ? w0 + 1 : w0;
-    return __builtin_amdgcn_alignbit(seq[w1], seq[w0], (uint32_t)(pos & 15) * 2u) & 0xFFFFFFu;
-}
-
 // reverse complement of a 12-mer (base i at bits 2i)
 __device__ __forceinline__ uint32_t rc24(uint32_t x)
 {
     const uint32_t r = __builtin_bitreverse32(x ^ 0xFFFFFFu) >> 8;
     return ((r & 0x555555u) << 1) | ((r >> 1) & 0x555555u);
+}
+
+// (t & 0x3FC) | base in one operation (base has no bits in 0x3FC); the
+// compiler turns the or of disjoint fields into an add and splits it up
+__device__ __forceinline__ uint32_t and_or_3fc(uint32_t t, uint32_t base)
+{
+    uint32_t r;
+    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(t), "s"(0x3FCu), "v"(base));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t tab_slot(uint32_t km)
+{
+    return (km * kGold24) >> 23;   // km < 2^24: a 24-bit multiply
 }
 
 __device__ __forceinline__ void lds_fence()
@@ -73,246 +97,334 @@ __device__ __forceinline__ void lds_fence()
     __builtin_amdgcn_wave_barrier();
 }
 
-struct CandStats {
-    uint32_t ndp, nh, nmode, nmode3, nbins, mode, gc, nf, strand;
-};
-
-// per-candidate feature f (0..63) other than the cross-candidate ones 39..44
-__device__ __forceinline__ float cand_feature(int f, const CandStats &S, const uint32_t *acc,
-                                              int P, int mf)
+// floor(16 x / d) for 0 <= x < d <= 1013, with r = RN(16 / d):
+// (x + 1/32) * 16 / d lies at least 1/(2d) from an integer and the float error
+// stays below 2^-18, so the truncation is exact.
+__device__ __forceinline__ uint32_t bin16(uint32_t x, float r)
 {
-    const float Pd = (float)max(P, 1);
-    const float nfd = (float)max((int)S.nf, 1);
-    if (f >= 7 && f < 39)
-        return (float)acc[2 + (f - 7)] / Pd;          // hist_p then hist_j are contiguous
-    switch (f) {
-    case 0: return (float)S.ndp / Pd;
-    case 1: return (float)min(S.nh, 4u * (uint32_t)max(P, 1)) / Pd;
-    case 2: return (float)S.nmode / Pd;
-    case 3: return (float)S.nmode3 / Pd;
-    case 4: return (float)min(S.nbins, 64u) / 16.f;
-    case 5: return S.nh ? (float)(16 * (int)S.mode + 8 - mf) / nfd : 0.f;
-    case 6: return S.nh ? 1.f : 0.f;
-    case 45: return (float)S.nf / 1000.f;
-    case 46: return (float)mf / 1000.f;
-    case 47: return (float)S.strand;
-    case 48: return (float)S.gc / nfd;
-    default: return 0.f;
-    }
+    return (uint32_t)__builtin_fmaf((float)x, r, r * 0.03125f);
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1)
+        v = max(v, (uint32_t)__shfl_xor((int)v, off));
+    return v;
 }
 
 __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, const uint32_t *first,
                                                            const uint32_t *count, uint16_t *feat)
 {
     __shared__ WaveLds lds_all[kWavesF];
+    // prefilter bitmaps, [wave][orientation][word]; a flat index keeps the
+    // per-position address at two operations
+    __shared__ uint32_t bm_all[kWavesF * 2 * kBm];
     WaveLds &L = lds_all[threadIdx.x >> 6];
+    const uint32_t bm_wave = (threadIdx.x >> 6) * 2 * kBm;
     const int lane = threadIdx.x & 63;
     const uint64_t ref_words = (b.ref_len + 15) / 16;
     const uint64_t read_words = (b.reads_len + 15) / 16;
-    const int slot = lane >> 4, sl = lane & 15;
+    // window rows start at zero; every group clears its rows after use
+    for (int i = lane; i < kG * kRow / 4; i += 64)
+        reinterpret_cast<uint4 *>(&L.acc[0][0])[i] = make_uint4(0, 0, 0, 0);
     for (uint32_t r = blockIdx.x * kWavesF + (threadIdx.x >> 6); r < b.n_reads;
          r += gridDim.x * kWavesF) {
         const uint32_t K = count[r];
         if (K == 0 || K > kMaxCand)
             continue;
         const uint32_t a = first[r];
-        uint32_t ok = 1;
-        for (uint32_t c = lane; c < K; c += 64)
-            ok &= (b.d_win[a + c].read_id == r) ? 1u : 0u;
-        if (!__all(ok))       // not contiguous: the decision keeps the whole read
-            continue;
         const int m_full = b.d_read_len[r];
         const uint64_t roff = b.d_read_off[r];
-        const int mf = min(m_full, kMF);
-        const int P = max(mf - kK + 1, 0);
-        // ---- query k-mer tables and prefilters (orientation 0: read, 1: reverse complement)
-        for (int i = lane; i < kTab; i += 64) {
-            L.key[0][i] = 0;
-            L.key[1][i] = 0;
-        }
-        for (int i = lane; i < kBm; i += 64) {
-            L.bm[0][i] = 0;
-            L.bm[1][i] = 0;
-        }
-        lds_fence();
-        for (int e = lane; e < 2 * P; e += 64) {
-            const int o = e >= P;
-            const int p = o ? e - P : e;
-            const uint32_t km = o ? rc24(kmer_at(b.d_reads2b, read_words, roff + (uint64_t)(m_full - p - kK)))
-                                  : kmer_at(b.d_reads2b, read_words, roff + (uint64_t)p);
-            const uint32_t H = km * kGold;
-            atomicOr(&L.bm[o][H >> 24], 1u << ((H >> 19) & 31u));
-            uint32_t h = H >> 23;
-            for (;;) {
-                const uint32_t old = atomicCAS(&L.key[o][h], 0u, km + 1u);
-                if (old == 0) {
-                    L.pos[o][h] = (uint16_t)p;
-                    break;
-                }
-                h = (h + 1) & (kTab - 1);
-            }
-        }
-        lds_fence();
-        // ---- candidate windows, four at a time
-        for (uint32_t c0 = 0; c0 < K; c0 += kSlots) {
-            const uint32_t c = c0 + slot;
-            const bool act = c < K;
-            const sw_window w = b.d_win[a + (act ? c : 0)];
+        // window descriptors of all candidates
+        uint32_t ok = 1;
+        if ((uint32_t)lane < K) {
+            const sw_window w = b.d_win[a + lane];
+            ok = w.read_id == r;
             int n = 0;
-            if (act && (uint64_t)w.ref_begin < b.ref_len) {
+            if ((uint64_t)w.ref_begin < b.ref_len) {
                 const uint64_t avail = b.ref_len - w.ref_begin;
                 n = w.len < avail ? (int)w.len : (int)avail;
             }
-            const int nf = min(n, kNF);
-            const int J = max(nf - kK + 1, 0);
-            const int nb = ((nf + mf) >> 4) + 2;
-            for (int i = sl; i < nb; i += 16)
-                L.bins[slot][i] = 0;
-            if (sl < kMF / 32)
-                L.pbits[slot][sl] = 0;
-            for (int i = sl; i < 36; i += 16)
-                L.acc[slot][i] = 0;
-            lds_fence();
-            const int o = w.strand ? 1 : 0;
-            const int Pd = max(P, 1), Jd = max(J, 1);
-            const uint64_t rb = w.ref_begin;
-            uint32_t gc = 0;
-            if (nf > 0) {
-                const uint64_t wfirst = rb >> 4, wlast = (rb + (uint64_t)nf - 1) >> 4;
-                for (uint64_t wd = wfirst + (uint64_t)sl; wd <= wlast; wd += 16) {
-                    const uint32_t u0 = b.d_ref2b[wd];
-                    const uint32_t u1 = b.d_ref2b[wd + 1 < ref_words ? wd + 1 : wd];
-                    const int j0 = (int)((int64_t)(wd * 16) - (int64_t)rb);   // window position of base 0
-                    uint32_t cand = 0;
+            L.wrb[lane] = w.ref_begin;
+            L.wnf[lane] = (uint16_t)min(n, kNF);
+            L.wst[lane] = w.strand;
+        }
+        if (!__all(ok))       // not contiguous: the decision keeps the whole read
+            continue;
+        const int mf = min(m_full, kMF);
+        const int P = max(mf - kK + 1, 0);
+        const float Pdf = (float)max(P, 1);
+        const float rP = 16.f / Pdf;
+        // words holding read bases [0, mf) and [m_full - mf, m_full) (for the reverse complement)
+        const uint64_t w_f0 = roff >> 4;
+        const uint64_t w_r0 = (roff + (uint64_t)(m_full - mf)) >> 4;
+        if (lane < kMF / 16 + 2)
+            L.rd[lane] = b.d_reads2b[min(w_f0 + (uint64_t)lane, read_words - 1)];
+        else if (lane >= 32 && lane < 32 + kMF / 16 + 2)
+            L.rr[lane - 32] = b.d_reads2b[min(w_r0 + (uint64_t)(lane - 32), read_words - 1)];
+        for (int i = lane; i < kTab; i += 64) {
+            L.tab[0][i] = 0xFFFFFFFFu;
+            L.tab[1][i] = 0xFFFFFFFFu;
+        }
+        for (int i = lane; i < 2 * kBm; i += 64)
+            bm_all[bm_wave + i] = 0;
+        for (int x = lane; x < 256; x += 64)
+            L.lut[x] = f2bf((float)x / Pdf);
+        lds_fence();
+        // ---- query k-mer tables and prefilters (orientation 0: read, 1: reverse complement)
+        for (int e = lane; e < 2 * P; e += 64) {
+            const int o = e >= P;
+            const int p = o ? e - P : e;
+            uint32_t km;
+            if (!o) {
+                const uint64_t pos = roff + (uint64_t)p - (w_f0 << 4);
+                km = __builtin_amdgcn_alignbit(L.rd[(pos >> 4) + 1], L.rd[pos >> 4],
+                                               (uint32_t)(pos & 15) * 2u) & 0xFFFFFFu;
+            } else {
+                // reverse complement of the read 12-mer at read position m_full - p - 12
+                const uint64_t pos = roff + (uint64_t)(m_full - p - kK) - (w_r0 << 4);
+                const int wi = (int)(pos >> 4);
+                km = rc24(__builtin_amdgcn_alignbit(L.rr[wi + 1], L.rr[wi], (uint32_t)(pos & 15) * 2u) &
+                          0xFFFFFFu);
+            }
+            atomicOr(&bm_all[bm_wave + o * kBm + ((km >> 5) & (kBm - 1))], 1u << (km & 31u));
+            const uint32_t entry = (km << 8) | (uint32_t)p;
+            uint32_t h = tab_slot(km);
+            while (atomicCAS(&L.tab[o][h], 0xFFFFFFFFu, entry) != 0xFFFFFFFFu)
+                h = (h + 1) & (kTab - 1);
+        }
+        lds_fence();
+        // x / max(P, 1) as bfloat16 for a signed integer numerator
+        auto over_p = [&](int32_t x) -> uint16_t {
+            const uint32_t ax = (uint32_t)(x < 0 ? -x : x);
+            uint16_t v;
+            if (ax < 256)
+                v = L.lut[ax];
+            else
+                v = f2bf((float)ax / Pdf);
+            return x < 0 ? (uint16_t)(v | 0x8000u) : v;
+        };
+        for (uint32_t cg = 0; cg < K; cg += kG) {
+            const int Gn = min((int)(K - cg), kG);
+            // ---- the group's words as one stream
+            uint32_t nw = 0;
+            if (lane < Gn) {
+                const int nf = L.wnf[cg + lane];
+                const uint64_t rb = L.wrb[cg + lane];
+                nw = nf > 0 ? (uint32_t)(((rb + (uint64_t)nf - 1) >> 4) - (rb >> 4) + 1) : 0u;
+                L.rj[lane] = 16.f / (float)max(nf - kK + 1, 1);
+            }
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const int j = j0 + i;
-                        const uint32_t km = __builtin_amdgcn_alignbit(u1, u0, 2u * i) & 0xFFFFFFu;
-                        const uint32_t base = km & 3u;
-                        gc += ((unsigned)j < (unsigned)nf && (base == 1u || base == 2u)) ? 1u : 0u;
-                        const uint32_t H = km * kGold;
-                        const uint32_t bit = (L.bm[o][H >> 24] >> ((H >> 19) & 31u)) & 1u;
-                        cand |= ((unsigned)j < (unsigned)J && bit) ? (1u << i) : 0u;
-                    }
-                    while (cand) {
-                        const int i = __builtin_ctz(cand);
-                        cand &= cand - 1;
-                        const int j = j0 + i;
-                        const uint32_t km = __builtin_amdgcn_alignbit(u1, u0, 2u * i) & 0xFFFFFFu;
-                        uint32_t h = (km * kGold) >> 23;
-                        for (;;) {
-                            const uint32_t key = L.key[o][h];
-                            if (key == 0)
-                                break;
-                            if (key == km + 1u) {
-                                const int p = L.pos[o][h];
-                                atomicAdd(&L.bins[slot][(j - p + mf) >> 4], 1u);
-                                atomicOr(&L.pbits[slot][p >> 5], 1u << (p & 31));
-                                atomicAdd(&L.acc[slot][0], 1u);
-                                atomicAdd(&L.acc[slot][2 + (16 * p) / Pd], 1u);
-                                atomicAdd(&L.acc[slot][18 + (16 * j) / Jd], 1u);
-                            }
-                            h = (h + 1) & (kTab - 1);
+            for (int off = 1; off < kG; off <<= 1) {
+                const uint32_t t = __shfl_up(nw, off, kG);
+                if ((lane & (kG - 1)) >= off)
+                    nw += t;
+            }
+            if (lane < kG)
+                L.cwo[lane + 1] = nw;
+            if (lane == 0)
+                L.cwo[0] = 0;
+            lds_fence();
+            const uint32_t total = L.cwo[Gn];
+            uint32_t c = 0, u0 = 0, u1 = 0;
+            // window of stream word wn (c only moves forward) and the word pair at it
+            auto fetch = [&](uint32_t wn) {
+                while (c + 1 < (uint32_t)Gn && L.cwo[c + 1] <= wn)
+                    ++c;
+                const uint64_t gw = (uint64_t)(L.wrb[cg + c] >> 4) + (uint64_t)(wn - L.cwo[c]);
+                u0 = b.d_ref2b[min(gw, ref_words - 1)];
+                u1 = b.d_ref2b[min(gw + 1, ref_words - 1)];
+            };
+            if ((uint32_t)lane < total)
+                fetch(lane);
+            for (uint32_t W = 0; W < total; W += 64) {
+                const uint32_t wc = W + lane, cc = c, a0 = u0, a1 = u1;
+                if (wc + 64 < total)
+                    fetch(wc + 64);
+                if (wc >= total)
+                    continue;
+                const uint32_t ci = cg + cc;
+                const uint32_t rb = L.wrb[ci];
+                const int nf = L.wnf[ci];
+                const int o = L.wst[ci] ? 1 : 0;
+                const int J = max(nf - kK + 1, 0);
+                const int j0 = 16 * (int)(wc - L.cwo[cc]) - (int)(rb & 15u);
+                // positions i of this word with 0 <= j0 + i < J (k-mers), < nf (bases)
+                const int lo = max(-j0, 0);
+                const int hiJ = min(J - j0, 16), hiN = min(nf - j0, 16);
+                const uint32_t vmask = hiJ > lo ? ((1u << hiJ) - 1u) & ~((1u << lo) - 1u) : 0u;
+                const uint32_t gmask =
+                    hiN > lo ? (uint32_t)(((1ull << (2 * hiN)) - 1ull) & ~((1ull << (2 * lo)) - 1ull)) : 0u;
+                uint32_t *A = L.acc[cc];
+                const uint32_t g = __popc((a0 ^ (a0 >> 1)) & 0x55555555u & gmask);   // C = 01, G = 10
+                if (g)
+                    atomicAdd(&A[kRowGc], g);
+                const uint32_t bmo = (bm_wave | (uint32_t)(o * kBm)) * 4u;   // byte offset, multiple of 1024
+                const uint32_t x16 = __builtin_amdgcn_alignbit(a1, a0, 16);
+                uint32_t cand = 0;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    // bits 0..12 of the k-mer at position i
+                    const uint32_t s = i < 10 ? (a0 >> (2 * i)) : (x16 >> (2 * i - 16));
+                    const uint32_t word = *reinterpret_cast<const uint32_t *>(
+                        reinterpret_cast<const char *>(bm_all) + and_or_3fc(s >> 3, bmo));
+                    cand |= __builtin_amdgcn_ubfe(word, s, 1u) << i;
+                }
+                cand &= vmask;
+                if (!cand)
+                    continue;
+                const uint32_t *tabo = L.tab[o];
+                const float rJ = L.rj[cc];
+                do {
+                    const int i = __builtin_ctz(cand);
+                    cand &= cand - 1u;
+                    const uint32_t km = __builtin_amdgcn_alignbit(a1, a0, 2u * (uint32_t)i) & 0xFFFFFFu;
+                    const int j = j0 + i;
+                    uint32_t h = tab_slot(km);
+                    for (;;) {
+                        const uint32_t e = tabo[h];
+                        if (e == 0xFFFFFFFFu)
+                            break;
+                        if ((e >> 8) == km) {
+                            const uint32_t p = e & 0xFFu;
+                            const uint32_t d = (uint32_t)(j + mf) - p;   // 16 * bin + offset
+                            atomicAdd(&A[kRowBins + (d >> 5)], 1u << (d & 16u));
+                            atomicOr(&A[kRowPbits + (p >> 5)], 1u << (p & 31u));
+                            atomicAdd(&A[7 + bin16(p, rP)], 1u);
+                            atomicAdd(&A[23 + bin16((uint32_t)j, rJ)], 1u);
                         }
+                        h = (h + 1) & (kTab - 1);
+                    }
+                } while (cand);
+            }
+            lds_fence();
+            // ---- statistics, four lanes per window
+            {
+                const int cw = lane >> 2, q = lane & 3;
+                const bool live = cw < Gn;
+                const uint32_t ci = cg + (live ? cw : 0);
+                const int nf = live ? (int)L.wnf[ci] : 0;
+                uint32_t *A = L.acc[cw];
+                const int nbw = (((nf + mf) >> 4) + 3) >> 1;   // words of bins 0 .. ((nf + mf) >> 4) + 1
+                uint32_t bestc = 0, besti = 0, nz = 0;
+                for (int wd = q; wd < nbw; wd += 4) {
+                    const uint32_t v = A[kRowBins + wd];
+                    const uint32_t v0 = v & 0xFFFFu, v1 = v >> 16;
+                    nz += (v0 ? 1u : 0u) + (v1 ? 1u : 0u);
+                    if (v0 > bestc) {
+                        bestc = v0;
+                        besti = 2 * wd;
+                    }
+                    if (v1 > bestc) {
+                        bestc = v1;
+                        besti = 2 * wd + 1;
+                    }
+                }
+                uint32_t ndp = __popc(A[kRowPbits + q]) + __popc(A[kRowPbits + 4 + q]);
+                uint32_t nh = A[7 + q] + A[11 + q] + A[15 + q] + A[19 + q];
+#pragma unroll
+                for (int off = 1; off < 4; off <<= 1) {
+                    const uint32_t oc = __shfl_xor(bestc, off);
+                    const uint32_t oi = __shfl_xor(besti, off);
+                    if (oc > bestc || (oc == bestc && oi < besti)) {
+                        bestc = oc;
+                        besti = oi;
+                    }
+                    nz += __shfl_xor(nz, off);
+                    ndp += __shfl_xor(ndp, off);
+                    nh += __shfl_xor(nh, off);
+                }
+                auto bin = [&](uint32_t k) { return (A[kRowBins + (k >> 1)] >> ((k & 1u) * 16u)) & 0xFFFFu; };
+                uint32_t nmode = 0, nmode3 = 0, mode = 0, nbins = 0;
+                if (nh) {
+                    mode = besti;
+                    nmode = bestc;
+                    nmode3 = bin(mode) + (mode ? bin(mode - 1) : 0u) + bin(mode + 1);
+                    nbins = nz;
+                }
+                if (live) {
+                    if (q == 0) {
+                        A[0] = ndp;
+                        A[1] = min(nh, 4u * (uint32_t)max(P, 1));
+                        A[2] = nmode;
+                        A[3] = nmode3;
+                    } else if (q == 1) {
+                        A[4] = f2bf((float)min(nbins, 64u) * 0.0625f);
+                        A[5] = nh ? f2bf((float)(16 * (int)mode + 8 - mf) / (float)max(nf, 1)) : 0u;
+                        A[6] = nh ? 0x3F80u : 0u;
+                    } else if (q == 2) {
+                        A[45] = f2bf((float)nf / 1000.f);
+                        A[46] = f2bf((float)mf / 1000.f);
+                        A[47] = L.wst[ci] ? 0x3F80u : 0u;
+                    } else {
+                        A[48] = f2bf((float)A[kRowGc] / (float)max(nf, 1));
+                        L.nm3[ci] = nmode3;
+                        L.ndp[ci] = ndp;
                     }
                 }
             }
-#pragma unroll
-            for (int off = 1; off < 16; off <<= 1)
-                gc += __shfl_xor(gc, off);
             lds_fence();
-            // modal bin (most hits, smallest index on ties) and occupied bins
-            uint32_t bestc = 0, besti = 0x7FFFFFFF, nz = 0;
-            for (int i = sl; i < nb; i += 16) {
-                const uint32_t v = L.bins[slot][i];
-                nz += v ? 1u : 0u;
-                if (v > bestc) {
-                    bestc = v;
-                    besti = i;
-                }
-            }
-            uint32_t ndp = sl < kMF / 32 ? __popc(L.pbits[slot][sl]) : 0u;
-#pragma unroll
-            for (int off = 1; off < 16; off <<= 1) {
-                const uint32_t oc = __shfl_xor(bestc, off);
-                const uint32_t oi = __shfl_xor(besti, off);
-                if (oc > bestc || (oc == bestc && oi < besti)) {
-                    bestc = oc;
-                    besti = oi;
-                }
-                nz += __shfl_xor(nz, off);
-                ndp += __shfl_xor(ndp, off);
-            }
-            if (act) {
-                CandStats S;
-                S.nh = L.acc[slot][0];
-                S.ndp = ndp;
-                S.mode = S.nh ? besti : 0u;
-                S.nmode = S.nh ? bestc : 0u;
-                S.nmode3 = S.nh ? L.bins[slot][S.mode] + (S.mode ? L.bins[slot][S.mode - 1] : 0u) +
-                                      L.bins[slot][S.mode + 1]
-                                : 0u;
-                S.nbins = nz;
-                S.gc = gc;
-                S.nf = (uint32_t)nf;
-                S.strand = w.strand;
-                uint16_t v[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    v[q] = f2bf(cand_feature(4 * sl + q, S, L.acc[slot], P, mf));
-                uint2 pk;
-                pk.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
-                pk.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
-                *reinterpret_cast<uint2 *>(feat + (uint64_t)(a + c) * kIn + 4 * sl) = pk;
-                if (sl == 0) {
-                    L.nm3[c] = S.nmode3;
-                    L.ndp[c] = S.ndp;
-                }
-            }
-            lds_fence();
-        }
-        // ---- features comparing the read's candidates (39..44)
-        uint32_t mx3 = 0, mxd = 0;
-        for (uint32_t c = lane; c < K; c += 64) {
-            mx3 = max(mx3, L.nm3[c]);
-            mxd = max(mxd, L.ndp[c]);
-        }
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            mx3 = max(mx3, (uint32_t)__shfl_xor((int)mx3, off));
-            mxd = max(mxd, (uint32_t)__shfl_xor((int)mxd, off));
-        }
-        uint32_t at_max = 0, second = 0;
-        for (uint32_t c = lane; c < K; c += 64) {
-            const uint32_t v = L.nm3[c];
-            at_max += v == mx3 ? 1u : 0u;
-            if (v != mx3)
-                second = max(second, v);
-        }
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            at_max += __shfl_xor(at_max, off);
-            second = max(second, (uint32_t)__shfl_xor((int)second, off));
-        }
-        if (at_max >= 2)
-            second = mx3;
-        const float Pd = (float)max(P, 1);
-        for (uint32_t idx = lane; idx < 6 * K; idx += 64) {
-            const uint32_t c = idx / 6;
-            const int f = 39 + (int)(idx % 6);
-            const uint32_t v3 = L.nm3[c];
-            float v;
-            if (f == 39) v = (float)((int)v3 - (int)mx3) / Pd;
-            else if (f == 40) v = (float)((int)L.ndp[c] - (int)mxd) / Pd;
-            else if (f == 41) v = v3 == mx3 ? 1.f : 0.f;
-            else if (f == 42) {
+            // ---- features comparing the read's windows (39..44), when the group is the whole read
+            if (K <= (uint32_t)kG) {
+                const bool in = (uint32_t)lane < K;
+                const uint32_t v3 = in ? L.nm3[lane] : 0u, dp = in ? L.ndp[lane] : 0u;
+                const uint32_t mx3 = wave_max(v3), mxd = wave_max(dp);
+                const uint64_t at = __ballot(in && v3 == mx3);
+                uint32_t second = wave_max(in && v3 != mx3 ? v3 : 0u);
+                if (__popcll(at) >= 2)
+                    second = mx3;
                 uint32_t gt = 0;
                 for (uint32_t d = 0; d < K; ++d)
                     gt += L.nm3[d] > v3 ? 1u : 0u;
-                v = (float)gt / (float)K;
-            } else if (f == 43) v = (float)(mx3 - second) / Pd;
-            else v = (float)K / 16.f;
-            feat[(uint64_t)(a + c) * kIn + f] = f2bf(v);
+                if (in) {
+                    uint32_t *A = L.acc[lane];
+                    A[39] = (uint32_t)((int32_t)v3 - (int32_t)mx3);
+                    A[40] = (uint32_t)((int32_t)dp - (int32_t)mxd);
+                    A[41] = v3 == mx3 ? 0x3F80u : 0u;
+                    A[42] = f2bf((float)gt / (float)K);
+                    A[43] = mx3 - second;
+                    A[44] = f2bf((float)K * 0.0625f);
+                }
+                lds_fence();
+            }
+            // ---- one 128-byte feature row per window: lane f writes feature f
+            {
+                const bool overp = (kOverP >> lane) & 1u;
+                const bool later = K > (uint32_t)kG && lane >= 39 && lane < 45;
+                for (int cw = 0; cw < Gn; ++cw) {
+                    const int32_t x = (int32_t)L.acc[cw][lane];
+                    const uint16_t v = overp ? over_p(x) : (uint16_t)x;
+                    if (!later)
+                        feat[(uint64_t)(a + cg + cw) * kIn + lane] = v;
+                }
+            }
+            lds_fence();
+            for (int i = lane; i < kG * kRow / 4; i += 64)
+                reinterpret_cast<uint4 *>(&L.acc[0][0])[i] = make_uint4(0, 0, 0, 0);
+            lds_fence();
+        }
+        // ---- features 39..44 of reads with more windows than a group
+        if (K > (uint32_t)kG) {
+            const bool in = (uint32_t)lane < K;
+            const uint32_t v3 = in ? L.nm3[lane] : 0u, dp = in ? L.ndp[lane] : 0u;
+            const uint32_t mx3 = wave_max(v3), mxd = wave_max(dp);
+            const uint64_t at = __ballot(in && v3 == mx3);
+            uint32_t second = wave_max(in && v3 != mx3 ? v3 : 0u);
+            if (__popcll(at) >= 2)
+                second = mx3;
+            uint32_t gt = 0;
+            for (uint32_t d = 0; d < K; ++d)
+                gt += L.nm3[d] > v3 ? 1u : 0u;
+            if (in) {
+                uint16_t *f = feat + (uint64_t)(a + lane) * kIn;
+                f[39] = over_p((int32_t)v3 - (int32_t)mx3);
+                f[40] = over_p((int32_t)dp - (int32_t)mxd);
+                f[41] = v3 == mx3 ? 0x3F80u : 0u;
+                f[42] = f2bf((float)gt / (float)K);
+                f[43] = over_p((int32_t)(mx3 - second));
+                f[44] = f2bf((float)K * 0.0625f);
+            }
         }
         lds_fence();
     }
@@ -326,7 +438,9 @@ hipError_t launch_features(const sw_batch &b, const uint32_t *first, const uint3
     if (b.n_reads == 0)
         return hipSuccess;
     uint32_t blocks = (b.n_reads + kWavesF - 1) / kWavesF;
-    const uint32_t cap = (uint32_t)n_cu * 8;
+    // as many resident blocks as the LDS of a compute unit holds
+    const uint32_t per_cu = (uint32_t)(160 * 1024 / (kWavesF * (sizeof(WaveLds) + 2 * kBm * 4)));
+    const uint32_t cap = (uint32_t)n_cu * (per_cu > 0 ? per_cu : 1);
     if (blocks > cap)
         blocks = cap;
     hipLaunchKernelGGL(k_features, dim3(blocks), dim3(64 * kWavesF), 0, st, b, first, count, feat);
