@@ -8,18 +8,22 @@
 // One wave per read.  The read's 12-mers, for both orientations, go into two
 // open-addressing hash tables in LDS (at most 245 k-mers in 512 slots each),
 // each with an 8192-bit prefilter bitmap indexed by the k-mer's first 6.5
-// bases.  The wave then takes the read's candidate windows sixteen at a time
-// and treats their reference words (16 bases each) as one flat stream: lane l
-// of a 64-word chunk owns word l of the stream, whatever window it belongs to,
-// so no lane idles at a window's end.  A lane forms the 16 k-mers that start in
-// its word with shifts of the word pair, tests all 16 against the bitmap (five
-// VALU operations each) and probes the table only for bitmap hits (true seed
-// matches plus about 3 % false positives).  Every hit (p, j) goes into the
-// window's LDS row: diagonal-bin counters (two 16-bit halves per word), a
-// bitmap of hit read positions and two 16-bin position histograms.  When the
-// group is done, four lanes per window reduce the row to the statistics, and
-// the wave writes one 128-byte feature row per window (lane f: feature f).
-// Features are computed in float32 and rounded to bfloat16.
+// bases.  The wave takes the read's candidate windows eight at a time and
+// treats their reference words (16 bases each) as one flat stream: lane l of
+// a 64-word chunk owns word l of the stream, whatever window it belongs to.  A
+// lane forms the 16 k-mers that start in its word with shifts of the word
+// pair and tests them against the bitmap (five VALU operations each).  The
+// bitmap hits of the whole chunk (true seed matches plus about 1.5 % false
+// positives) are compacted into an LDS list with a wave prefix sum and probed
+// 64 at a time, so the dense hits of a true window spread over all lanes
+// instead of queueing in the few lanes that own its words.  Every hit (p, j)
+// goes into the window's LDS row: diagonal-bin counters (two 16-bit halves
+// per word), a bitmap of hit read positions and two 16-bin position
+// histograms.  When the group is done, eight lanes per window reduce the row
+// to the statistics, and the wave writes one 128-byte feature row per window
+// (lane f: feature f).  The next read's descriptors and packed words are
+// loaded while the current read is processed.  Features are computed in
+// float32 and rounded to bfloat16.
 #include "mlp_internal.h"
 
 namespace hpgsw {
@@ -31,9 +35,11 @@ constexpr int kMF = 256;           // query bases used
 constexpr int kNF = 1024;          // window bases used
 constexpr int kTab = 512;          // hash slots per orientation
 constexpr int kBm = 256;           // prefilter bitmap words per orientation (8192 bits)
-constexpr int kG = 16;             // windows per group
+constexpr int kG = 8;              // windows per group
+constexpr int kList = 192;         // bitmap candidates probed per pass
 constexpr int kWavesF = 2;         // waves per block
 constexpr uint32_t kGold24 = 0x9E3779u;   // odd 24-bit multiplier of the table hash
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
 // Row of one window (32-bit words).  Words 0..63 are its feature row: for the
 // features divided by max(P, 1) a word holds the integer numerator, for the
@@ -47,10 +53,12 @@ constexpr int kRow = 116;
 constexpr uint64_t kOverP = 0xFull | (((1ull << 34) - 1) << 7) | (1ull << 43);
 
 static_assert((kNF + kMF) / 32 + 2 <= kRowPbits - kRowBins, "diagonal bins do not fit the row");
+static_assert(kG <= 16, "window index of a list entry has 4 bits");
 
 struct alignas(16) WaveLds {
-    uint32_t tab[2][kTab];         // (k-mer << 8) | read position, 0xFFFFFFFF = empty
+    uint32_t tab[2][kTab];         // (k-mer << 8) | read position, kEmpty = empty
     uint32_t acc[kG][kRow];
+    uint2 list[kList];             // (k-mer | window << 24 | orientation << 28, j)
     uint16_t lut[256];             // bfloat16 of x / max(P, 1)
     uint32_t rd[kMF / 16 + 2];     // packed words holding the read's first 256 bases
     uint32_t rr[kMF / 16 + 2];     // packed words holding its last 256 bases
@@ -120,38 +128,85 @@ __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, con
     // prefilter bitmaps, [wave][orientation][word]; a flat index keeps the
     // per-position address at two operations
     __shared__ uint32_t bm_all[kWavesF * 2 * kBm];
-    WaveLds &L = lds_all[threadIdx.x >> 6];
-    const uint32_t bm_wave = (threadIdx.x >> 6) * 2 * kBm;
+    const uint32_t wave = threadIdx.x >> 6;
+    WaveLds &L = lds_all[wave];
+    const uint32_t bm_wave = wave * 2 * kBm;
     const int lane = threadIdx.x & 63;
     const uint64_t ref_words = (b.ref_len + 15) / 16;
     const uint64_t read_words = (b.reads_len + 15) / 16;
     // window rows start at zero; every group clears its rows after use
     for (int i = lane; i < kG * kRow / 4; i += 64)
         reinterpret_cast<uint4 *>(&L.acc[0][0])[i] = make_uint4(0, 0, 0, 0);
-    for (uint32_t r = blockIdx.x * kWavesF + (threadIdx.x >> 6); r < b.n_reads;
-         r += gridDim.x * kWavesF) {
-        const uint32_t K = count[r];
-        if (K == 0 || K > kMaxCand)
-            continue;
-        const uint32_t a = first[r];
-        const int m_full = b.d_read_len[r];
-        const uint64_t roff = b.d_read_off[r];
-        // window descriptors of all candidates
-        uint32_t ok = 1;
-        if ((uint32_t)lane < K) {
-            const sw_window w = b.d_win[a + lane];
-            ok = w.read_id == r;
-            int n = 0;
-            if ((uint64_t)w.ref_begin < b.ref_len) {
-                const uint64_t avail = b.ref_len - w.ref_begin;
-                n = w.len < avail ? (int)w.len : (int)avail;
-            }
-            L.wrb[lane] = w.ref_begin;
-            L.wnf[lane] = (uint16_t)min(n, kNF);
-            L.wst[lane] = w.strand;
+    // A read's scalars, window descriptors and packed words are loaded one read
+    // ahead, so their latency overlaps the work on the previous read.
+    auto load_scalars = [&](uint32_t rx, uint32_t &Kx, uint32_t &ax, int &mx, uint64_t &ox) {
+        Kx = 0;
+        ax = 0;
+        mx = 0;
+        ox = 0;
+        if (rx < b.n_reads) {
+            Kx = count[rx];
+            ax = first[rx];
+            mx = b.d_read_len[rx];
+            ox = b.d_read_off[rx];
         }
-        if (!__all(ok))       // not contiguous: the decision keeps the whole read
+    };
+    sw_window wd{};
+    uint32_t rw = 0;
+    auto load_body = [&](uint32_t Kx, uint32_t ax, int mx, uint64_t ox) {
+        if ((uint32_t)lane < Kx && Kx <= (uint32_t)kMaxCand)
+            wd = b.d_win[ax + lane];
+        if (read_words == 0)
+            return;
+        const int mfx = min(mx, kMF);
+        const uint64_t wf = ox >> 4, wr = (ox + (uint64_t)(mx - mfx)) >> 4;
+        if (lane < kMF / 16 + 2)
+            rw = b.d_reads2b[min(wf + (uint64_t)lane, read_words - 1)];
+        else if (lane >= 32 && lane < 32 + kMF / 16 + 2)
+            rw = b.d_reads2b[min(wr + (uint64_t)(lane - 32), read_words - 1)];
+    };
+    const uint32_t stride = gridDim.x * kWavesF;
+    uint32_t r = blockIdx.x * kWavesF + wave;
+    uint32_t K, a;
+    int m_full;
+    uint64_t roff;
+    load_scalars(r, K, a, m_full, roff);
+    load_body(K, a, m_full, roff);
+    for (; r < b.n_reads; r += stride) {
+        // use up the registers loaded for this read before the next loads are issued
+        // (the load counter is in order: a wait for an older load drains newer ones)
+        bool go = K != 0 && K <= (uint32_t)kMaxCand;
+        if (go) {
+            uint32_t ok = 1;
+            if ((uint32_t)lane < K) {
+                ok = wd.read_id == r;
+                int n = 0;
+                if ((uint64_t)wd.ref_begin < b.ref_len) {
+                    const uint64_t avail = b.ref_len - wd.ref_begin;
+                    n = wd.len < avail ? (int)wd.len : (int)avail;
+                }
+                L.wrb[lane] = wd.ref_begin;
+                L.wnf[lane] = (uint16_t)min(n, kNF);
+                L.wst[lane] = wd.strand;
+            }
+            go = __all(ok);   // not contiguous: the decision keeps the whole read
+            if (lane < kMF / 16 + 2)
+                L.rd[lane] = rw;
+            else if (lane >= 32 && lane < 32 + kMF / 16 + 2)
+                L.rr[lane - 32] = rw;
+        }
+        uint32_t Kn, an;
+        int mn;
+        uint64_t on;
+        load_scalars(r + stride, Kn, an, mn, on);
+        if (!go) {
+            load_body(Kn, an, mn, on);
+            K = Kn;
+            a = an;
+            m_full = mn;
+            roff = on;
             continue;
+        }
         const int mf = min(m_full, kMF);
         const int P = max(mf - kK + 1, 0);
         const float Pdf = (float)max(P, 1);
@@ -159,13 +214,9 @@ __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, con
         // words holding read bases [0, mf) and [m_full - mf, m_full) (for the reverse complement)
         const uint64_t w_f0 = roff >> 4;
         const uint64_t w_r0 = (roff + (uint64_t)(m_full - mf)) >> 4;
-        if (lane < kMF / 16 + 2)
-            L.rd[lane] = b.d_reads2b[min(w_f0 + (uint64_t)lane, read_words - 1)];
-        else if (lane >= 32 && lane < 32 + kMF / 16 + 2)
-            L.rr[lane - 32] = b.d_reads2b[min(w_r0 + (uint64_t)(lane - 32), read_words - 1)];
         for (int i = lane; i < kTab; i += 64) {
-            L.tab[0][i] = 0xFFFFFFFFu;
-            L.tab[1][i] = 0xFFFFFFFFu;
+            L.tab[0][i] = kEmpty;
+            L.tab[1][i] = kEmpty;
         }
         for (int i = lane; i < 2 * kBm; i += 64)
             bm_all[bm_wave + i] = 0;
@@ -173,6 +224,7 @@ __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, con
             L.lut[x] = f2bf((float)x / Pdf);
         lds_fence();
         // ---- query k-mer tables and prefilters (orientation 0: read, 1: reverse complement)
+        uint32_t dupf = 0;   // bit o: a k-mer of orientation o occurs twice in the query
         for (int e = lane; e < 2 * P; e += 64) {
             const int o = e >= P;
             const int p = o ? e - P : e;
@@ -191,10 +243,18 @@ __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, con
             atomicOr(&bm_all[bm_wave + o * kBm + ((km >> 5) & (kBm - 1))], 1u << (km & 31u));
             const uint32_t entry = (km << 8) | (uint32_t)p;
             uint32_t h = tab_slot(km);
-            while (atomicCAS(&L.tab[o][h], 0xFFFFFFFFu, entry) != 0xFFFFFFFFu)
+            for (;;) {
+                const uint32_t old = atomicCAS(&L.tab[o][h], kEmpty, entry);
+                if (old == kEmpty)
+                    break;
+                if ((old >> 8) == km)
+                    dupf |= 1u << o;
                 h = (h + 1) & (kTab - 1);
+            }
         }
+        const bool dup0 = __ballot(dupf & 1u) != 0, dup1 = __ballot(dupf & 2u) != 0;
         lds_fence();
+        load_body(Kn, an, mn, on);
         // x / max(P, 1) as bfloat16 for a signed integer numerator
         auto over_p = [&](int32_t x) -> uint16_t {
             const uint32_t ax = (uint32_t)(x < 0 ? -x : x);
@@ -242,89 +302,124 @@ __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, con
                 const uint32_t wc = W + lane, cc = c, a0 = u0, a1 = u1;
                 if (wc + 64 < total)
                     fetch(wc + 64);
-                if (wc >= total)
-                    continue;
-                const uint32_t ci = cg + cc;
-                const uint32_t rb = L.wrb[ci];
-                const int nf = L.wnf[ci];
-                const int o = L.wst[ci] ? 1 : 0;
-                const int J = max(nf - kK + 1, 0);
-                const int j0 = 16 * (int)(wc - L.cwo[cc]) - (int)(rb & 15u);
-                // positions i of this word with 0 <= j0 + i < J (k-mers), < nf (bases)
-                const int lo = max(-j0, 0);
-                const int hiJ = min(J - j0, 16), hiN = min(nf - j0, 16);
-                const uint32_t vmask = hiJ > lo ? ((1u << hiJ) - 1u) & ~((1u << lo) - 1u) : 0u;
-                const uint32_t gmask =
-                    hiN > lo ? (uint32_t)(((1ull << (2 * hiN)) - 1ull) & ~((1ull << (2 * lo)) - 1ull)) : 0u;
-                uint32_t *A = L.acc[cc];
-                const uint32_t g = __popc((a0 ^ (a0 >> 1)) & 0x55555555u & gmask);   // C = 01, G = 10
-                if (g)
-                    atomicAdd(&A[kRowGc], g);
-                const uint32_t bmo = (bm_wave | (uint32_t)(o * kBm)) * 4u;   // byte offset, multiple of 1024
-                const uint32_t x16 = __builtin_amdgcn_alignbit(a1, a0, 16);
-                uint32_t cand = 0;
+                uint32_t cand = 0, head = 0;
+                int j0 = 0;
+                if (wc < total) {
+                    const uint32_t ci = cg + cc;
+                    const uint32_t rb = L.wrb[ci];
+                    const int nf = L.wnf[ci];
+                    const int o = L.wst[ci] ? 1 : 0;
+                    const int J = max(nf - kK + 1, 0);
+                    j0 = 16 * (int)(wc - L.cwo[cc]) - (int)(rb & 15u);
+                    // positions i of this word with 0 <= j0 + i < J (k-mers), < nf (bases)
+                    const int lo = max(-j0, 0);
+                    const int hiJ = min(J - j0, 16), hiN = min(nf - j0, 16);
+                    const uint32_t vmask = hiJ > lo ? ((1u << hiJ) - 1u) & ~((1u << lo) - 1u) : 0u;
+                    const uint32_t gmask =
+                        hiN > lo ? (uint32_t)(((1ull << (2 * hiN)) - 1ull) & ~((1ull << (2 * lo)) - 1ull))
+                                 : 0u;
+                    const uint32_t g = __popc((a0 ^ (a0 >> 1)) & 0x55555555u & gmask);   // C = 01, G = 10
+                    if (g)
+                        atomicAdd(&L.acc[cc][kRowGc], g);
+                    const uint32_t bmo = (bm_wave | (uint32_t)(o * kBm)) * 4u;   // bytes, multiple of 1024
+                    const uint32_t x16 = __builtin_amdgcn_alignbit(a1, a0, 16);
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    // bits 0..12 of the k-mer at position i
-                    const uint32_t s = i < 10 ? (a0 >> (2 * i)) : (x16 >> (2 * i - 16));
-                    const uint32_t word = *reinterpret_cast<const uint32_t *>(
-                        reinterpret_cast<const char *>(bm_all) + and_or_3fc(s >> 3, bmo));
-                    cand |= __builtin_amdgcn_ubfe(word, s, 1u) << i;
-                }
-                cand &= vmask;
-                if (!cand)
-                    continue;
-                const uint32_t *tabo = L.tab[o];
-                const float rJ = L.rj[cc];
-                do {
-                    const int i = __builtin_ctz(cand);
-                    cand &= cand - 1u;
-                    const uint32_t km = __builtin_amdgcn_alignbit(a1, a0, 2u * (uint32_t)i) & 0xFFFFFFu;
-                    const int j = j0 + i;
-                    uint32_t h = tab_slot(km);
-                    for (;;) {
-                        const uint32_t e = tabo[h];
-                        if (e == 0xFFFFFFFFu)
-                            break;
-                        if ((e >> 8) == km) {
-                            const uint32_t p = e & 0xFFu;
-                            const uint32_t d = (uint32_t)(j + mf) - p;   // 16 * bin + offset
-                            atomicAdd(&A[kRowBins + (d >> 5)], 1u << (d & 16u));
-                            atomicOr(&A[kRowPbits + (p >> 5)], 1u << (p & 31u));
-                            atomicAdd(&A[7 + bin16(p, rP)], 1u);
-                            atomicAdd(&A[23 + bin16((uint32_t)j, rJ)], 1u);
-                        }
-                        h = (h + 1) & (kTab - 1);
+                    for (int i = 0; i < 16; ++i) {
+                        // bits 0..12 of the k-mer at position i
+                        const uint32_t s = i < 10 ? (a0 >> (2 * i)) : (x16 >> (2 * i - 16));
+                        const uint32_t word = *reinterpret_cast<const uint32_t *>(
+                            reinterpret_cast<const char *>(bm_all) + and_or_3fc(s >> 3, bmo));
+                        cand |= __builtin_amdgcn_ubfe(word, s, 1u) << i;
                     }
-                } while (cand);
+                    cand &= vmask;
+                    head = (cc | (uint32_t)o << 4) << 24;
+                }
+                // offsets of every lane's candidates in the chunk's list (prefix over the wave)
+                const uint32_t cnt = __popc(cand);
+                uint32_t off = 0, tot = 0;
+#pragma unroll
+                for (int bp = 0; bp < 5; ++bp) {
+                    const uint64_t m = __ballot((cnt >> bp) & 1u);
+                    off += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << bp;
+                    tot += (uint32_t)__popcll(m) << bp;
+                }
+                for (uint32_t base = 0; base < tot; base += kList) {
+                    if (cand && off < base + kList && off + cnt > base) {
+                        uint32_t cm = cand, o2 = off;
+                        do {
+                            const int i = __builtin_ctz(cm);
+                            cm &= cm - 1u;
+                            if (o2 >= base + kList)
+                                break;
+                            if (o2 >= base) {
+                                const uint32_t km =
+                                    __builtin_amdgcn_alignbit(a1, a0, 2u * (uint32_t)i) & 0xFFFFFFu;
+                                L.list[o2 - base] = make_uint2(km | head, (uint32_t)(j0 + i));
+                            }
+                            ++o2;
+                        } while (cm);
+                    }
+                    lds_fence();
+                    // probe the listed k-mers, 64 at a time
+                    const uint32_t nq = min(tot - base, (uint32_t)kList);
+                    for (uint32_t q = lane; q < nq; q += 64) {
+                        const uint2 en = L.list[q];
+                        const uint32_t km = en.x & 0xFFFFFFu;
+                        const uint32_t cw = (en.x >> 24) & 15u, oo = en.x >> 28;
+                        const uint32_t j = en.y;
+                        const uint32_t *tabo = L.tab[oo];
+                        const bool dup = oo ? dup1 : dup0;
+                        uint32_t *A = L.acc[cw];
+                        const float rJ = L.rj[cw];
+                        uint32_t h = tab_slot(km);
+                        for (;;) {
+                            const uint32_t t = tabo[h];
+                            if (t == kEmpty)
+                                break;
+                            if ((t >> 8) == km) {
+                                const uint32_t p = t & 0xFFu;
+                                const uint32_t d = j + (uint32_t)mf - p;   // 16 * bin + offset
+                                atomicAdd(&A[kRowBins + (d >> 5)], 1u << (d & 16u));
+                                atomicOr(&A[kRowPbits + (p >> 5)], 1u << (p & 31u));
+                                atomicAdd(&A[7 + bin16(p, rP)], 1u);
+                                atomicAdd(&A[23 + bin16(j, rJ)], 1u);
+                                if (!dup)      // a k-mer that occurs once matches once
+                                    break;
+                            }
+                            h = (h + 1) & (kTab - 1);
+                        }
+                    }
+                    lds_fence();
+                }
             }
             lds_fence();
-            // ---- statistics, four lanes per window
+            // ---- statistics, eight lanes per window
             {
-                const int cw = lane >> 2, q = lane & 3;
+                const int cw = lane >> 3, q = lane & 7;
                 const bool live = cw < Gn;
                 const uint32_t ci = cg + (live ? cw : 0);
                 const int nf = live ? (int)L.wnf[ci] : 0;
                 uint32_t *A = L.acc[cw];
                 const int nbw = (((nf + mf) >> 4) + 3) >> 1;   // words of bins 0 .. ((nf + mf) >> 4) + 1
                 uint32_t bestc = 0, besti = 0, nz = 0;
-                for (int wd = q; wd < nbw; wd += 4) {
-                    const uint32_t v = A[kRowBins + wd];
+                for (int w = q; w < nbw; w += 8) {
+                    const uint32_t v = A[kRowBins + w];
                     const uint32_t v0 = v & 0xFFFFu, v1 = v >> 16;
                     nz += (v0 ? 1u : 0u) + (v1 ? 1u : 0u);
                     if (v0 > bestc) {
                         bestc = v0;
-                        besti = 2 * wd;
+                        besti = 2 * w;
                     }
                     if (v1 > bestc) {
                         bestc = v1;
-                        besti = 2 * wd + 1;
+                        besti = 2 * w + 1;
                     }
                 }
-                uint32_t ndp = __popc(A[kRowPbits + q]) + __popc(A[kRowPbits + 4 + q]);
-                uint32_t nh = A[7 + q] + A[11 + q] + A[15 + q] + A[19 + q];
+                uint32_t ndp = __popc(A[kRowPbits + q]);
+                uint32_t nh = A[7 + q] + A[15 + q];
 #pragma unroll
-                for (int off = 1; off < 4; off <<= 1) {
+                for (int off = 1; off < 8; off <<= 1) {
                     const uint32_t oc = __shfl_xor(bestc, off);
                     const uint32_t oi = __shfl_xor(besti, off);
                     if (oc > bestc || (oc == bestc && oi < besti)) {
@@ -357,7 +452,7 @@ __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, con
                         A[45] = f2bf((float)nf / 1000.f);
                         A[46] = f2bf((float)mf / 1000.f);
                         A[47] = L.wst[ci] ? 0x3F80u : 0u;
-                    } else {
+                    } else if (q == 3) {
                         A[48] = f2bf((float)A[kRowGc] / (float)max(nf, 1));
                         L.nm3[ci] = nmode3;
                         L.ndp[ci] = ndp;
@@ -427,6 +522,10 @@ __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, con
             }
         }
         lds_fence();
+        K = Kn;
+        a = an;
+        m_full = mn;
+        roff = on;
     }
 }
 

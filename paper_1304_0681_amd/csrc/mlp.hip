@@ -61,17 +61,43 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
 // ---------------------------------------------------------------------------
 constexpr int kInferWaves = 4;
 
-__global__ void __launch_bounds__(64 * kInferWaves)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// two floats -> packed bfloat16 pair (round to nearest even, one instruction)
+__device__ __forceinline__ uint32_t pk_bf16(float lo, float hi)
+{
+    const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// sum over the 16 lanes of a row, left in the row's last lane
+__device__ __forceinline__ float row_sum16(float v)
+{
+    v += __builtin_amdgcn_update_dpp(0.f, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0.f, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0.f, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0.f, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    return v;
+}
+
+__global__ void __launch_bounds__(64 * kInferWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_mlp_infer(const MlpDev W, const uint16_t *__restrict__ X, uint32_t n, const uint32_t *d_n,
             float *__restrict__ logits)
 {
     __shared__ uint16_t h1s[kInferWaves][16][kHidden + 8];   // +8: spread LDS banks
+    __shared__ float b1s[kHidden], b2s[kHidden], w3s[kHidden];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int li = lane & 15;      // row of A / column of B and D
     const int lk = lane >> 4;      // k group (8 wide) / row group of D
     if (d_n)
         n = min(n, *d_n);
+    for (int i = threadIdx.x; i < kHidden; i += 64 * kInferWaves) {
+        b1s[i] = W.b1[i];
+        b2s[i] = W.b2[i];
+        w3s[i] = bf2f(W.w3b[i]);
+    }
+    __syncthreads();
     // weight fragments: W1T is [128 out][64 in], W2T is [128 out][128 in]
     bf16x8 w1[8][2], w2[8][4];
 #pragma unroll
@@ -83,32 +109,38 @@ k_mlp_infer(const MlpDev W, const uint16_t *__restrict__ X, uint32_t n, const ui
         for (int kk = 0; kk < 4; ++kk)
             w2[nt][kk] = load8(W.w2t + (nt * 16 + li) * kHidden + kk * 32 + lk * 8);
     }
-    float b1v[8], b2v[8], w3v[8];
-#pragma unroll
-    for (int nt = 0; nt < 8; ++nt) {
-        b1v[nt] = W.b1[nt * 16 + li];
-        b2v[nt] = W.b2[nt * 16 + li];
-        w3v[nt] = bf2f(W.w3b[nt * 16 + li]);
-    }
     const float b3 = W.b3[0];
     const uint32_t n_tiles = (n + 15) / 16;
-    for (uint32_t tile = blockIdx.x * kInferWaves + wv; tile < n_tiles;
-         tile += gridDim.x * kInferWaves) {
-        const uint32_t row = tile * 16 + li;
-        bf16x8 xa[2];
+    const uint32_t stride = gridDim.x * kInferWaves;
+    uint32_t tile = blockIdx.x * kInferWaves + wv;
+    // the next tile's inputs are loaded while the current one is computed
+    bf16x8 xn[2];
+    auto load_x = [&](uint32_t t) {
+        const uint32_t row = t * 16 + li;
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk)
-            xa[kk] = row < n ? load8(X + (uint64_t)row * kIn + kk * 32 + lk * 8) : zero8();
-        // layer 1
+            xn[kk] = row < n ? load8(X + (uint64_t)row * kIn + kk * 32 + lk * 8) : zero8();
+    };
+    if (tile < n_tiles)
+        load_x(tile);
+    for (; tile < n_tiles; tile += stride) {
+        // layer 1: D(sample lk*4 + r, unit nt*16 + li), bias as the accumulator's start
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            acc = mfma(xa[0], w1[nt][0], acc);
-            acc = mfma(xa[1], w1[nt][1], acc);
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                h1s[wv][lk * 4 + r][nt * 16 + li] = f2bf(fmaxf(acc[r] + b1v[nt], 0.f));
+            const float b1 = b1s[nt * 16 + li];
+            f32x4 acc = {b1, b1, b1, b1};
+            acc = mfma(xn[0], w1[nt][0], acc);
+            acc = mfma(xn[1], w1[nt][1], acc);
+            const uint32_t h01 = pk_bf16(fmaxf(acc[0], 0.f), fmaxf(acc[1], 0.f));
+            const uint32_t h23 = pk_bf16(fmaxf(acc[2], 0.f), fmaxf(acc[3], 0.f));
+            h1s[wv][lk * 4 + 0][nt * 16 + li] = (uint16_t)h01;
+            h1s[wv][lk * 4 + 1][nt * 16 + li] = (uint16_t)(h01 >> 16);
+            h1s[wv][lk * 4 + 2][nt * 16 + li] = (uint16_t)h23;
+            h1s[wv][lk * 4 + 3][nt * 16 + li] = (uint16_t)(h23 >> 16);
         }
+        // the inputs are consumed: start loading the next tile's
+        if (tile + stride < n_tiles)
+            load_x(tile + stride);
         __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): LDS writes done (same wave)
         __builtin_amdgcn_wave_barrier();
         bf16x8 ha[4];
@@ -119,21 +151,22 @@ k_mlp_infer(const MlpDev W, const uint16_t *__restrict__ X, uint32_t n, const ui
         float part[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const float b2 = b2s[nt * 16 + li], w3 = w3s[nt * 16 + li];
+            f32x4 acc = {b2, b2, b2, b2};
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk)
                 acc = mfma(ha[kk], w2[nt][kk], acc);
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                part[r] += bf2f(f2bf(fmaxf(acc[r] + b2v[nt], 0.f))) * w3v[nt];
+            const uint32_t h01 = pk_bf16(fmaxf(acc[0], 0.f), fmaxf(acc[1], 0.f));
+            const uint32_t h23 = pk_bf16(fmaxf(acc[2], 0.f), fmaxf(acc[3], 0.f));
+            part[0] += __builtin_bit_cast(float, h01 << 16) * w3;
+            part[1] += __builtin_bit_cast(float, h01 & 0xFFFF0000u) * w3;
+            part[2] += __builtin_bit_cast(float, h23 << 16) * w3;
+            part[3] += __builtin_bit_cast(float, h23 & 0xFFFF0000u) * w3;
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-#pragma unroll
-            for (int off = 1; off < 16; off <<= 1)
-                part[r] += __shfl_xor(part[r], off);
-        }
-        if (li == 0) {
+        for (int r = 0; r < 4; ++r)
+            part[r] = row_sum16(part[r]);
+        if (li == 15) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const uint32_t rr = tile * 16 + lk * 4 + r;
@@ -550,7 +583,7 @@ hipError_t mlp_infer(const MlpDev &W, const uint16_t *X, uint32_t n, const uint3
         return hipSuccess;
     const uint32_t tiles = (n + 15) / 16;
     uint32_t blocks = (tiles + kInferWaves - 1) / kInferWaves;
-    const uint32_t cap = (uint32_t)n_cu * 4;
+    const uint32_t cap = (uint32_t)n_cu * 2;   // two waves per SIMD fit the register file
     if (blocks > cap)
         blocks = cap;
     hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(64 * kInferWaves), 0, st, W, X, n, d_n, logits);
