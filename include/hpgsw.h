@@ -194,6 +194,8 @@ typedef struct sw_mlp sw_mlp;
 
 typedef struct {
     float logit_lo, logit_hi;   /* unsure band [lo, hi); keep logits >= hi */
+    float logit_drop;           /* reads whose best logit is below this keep no
+                                   candidate (-INFINITY: never); <= logit_lo */
 } sw_filter_params;
 
 sw_status sw_mlp_create(sw_ctx *ctx, sw_mlp **out);
@@ -226,9 +228,13 @@ sw_status sw_mlp_labels(sw_ctx *ctx, const sw_batch *batch, const sw_hit *d_hits
                         const int32_t *d_best_score, int32_t margin, float *d_y, void *stream);
 
 /* Filter step: features (into d_feat[n_pairs * 64]), logits (d_logits[n_pairs]),
- * per-read decision (d_keep[n_pairs]: a read is unsure when its best logit is
- * below logit_hi or any logit lies in [logit_lo, logit_hi); unsure reads keep
- * every candidate, others keep the candidates with logit >= logit_hi) and
+ * per-read decision (d_keep[n_pairs]: a read whose best logit is below
+ * logit_drop keeps no candidate, so sw_best_per_read reports it without a hit,
+ * i.e. unmapped (stage E task iv records only alignments above the mapping
+ * threshold); otherwise a read is unsure when its best logit is below
+ * logit_hi or any logit lies in [logit_lo, logit_hi); unsure reads keep every
+ * candidate, others keep the candidates with logit >= logit_hi; reads whose
+ * pairs are not contiguous or number more than 64 keep every candidate) and
  * stable compaction of the kept pairs into d_win_out / d_sel_ids (original
  * pair index), with their number in *d_n_sel.  *d_n_unsure (device, may be
  * NULL) is incremented by the number of unsure reads.  The kept list is ready

@@ -56,7 +56,8 @@ class sw_batch(ctypes.Structure):
 
 
 class sw_filter_params(ctypes.Structure):
-    _fields_ = [("logit_lo", ctypes.c_float), ("logit_hi", ctypes.c_float)]
+    _fields_ = [("logit_lo", ctypes.c_float), ("logit_hi", ctypes.c_float),
+                ("logit_drop", ctypes.c_float)]
 
 
 SW_FEATURES = 64
@@ -223,8 +224,9 @@ def sw_mlp_labels(ctx, batch, d_hits, d_best_score, margin, d_y, stream=None):
 
 
 def sw_filter_candidates(ctx, batch, mlp, logit_lo, logit_hi, d_feat, d_logits, d_keep,
-                         d_win_out, d_sel_ids, d_n_sel, d_n_unsure=None, stream=None):
-    fp = sw_filter_params(float(logit_lo), float(logit_hi))
+                         d_win_out, d_sel_ids, d_n_sel, d_n_unsure=None, stream=None,
+                         logit_drop=float("-inf")):
+    fp = sw_filter_params(float(logit_lo), float(logit_hi), float(logit_drop))
     _check(ctx, lib().sw_filter_candidates(ctx, ctypes.byref(batch.c), mlp, ctypes.byref(fp),
                                            _ptr(d_feat), _ptr(d_logits), _ptr(d_keep),
                                            _ptr(d_win_out), _ptr(d_sel_ids), _ptr(d_n_sel),

@@ -677,6 +677,8 @@ sw_status sw_filter_candidates(sw_ctx *ctx, const sw_batch *b, const sw_mlp *mlp
         return fail(ctx, SW_E_INVALID, "NULL argument");
     if (!(fp->logit_lo <= fp->logit_hi))
         return fail(ctx, SW_E_INVALID, "logit_lo must not exceed logit_hi");
+    if (!(fp->logit_drop <= fp->logit_lo))
+        return fail(ctx, SW_E_INVALID, "logit_drop must not exceed logit_lo");
     if (b->d_n_pairs)
         return fail(ctx, SW_E_INVALID, "the filter takes a batch with a host pair count");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -693,7 +695,7 @@ sw_status sw_filter_candidates(sw_ctx *ctx, const sw_batch *b, const sw_mlp *mlp
     HIP_TRY(ctx, mlp_infer(mlp->dev(), d_feat, b->n_pairs, nullptr, d_logits, ctx->n_cu, s));
     uint32_t *unsure = d_n_unsure ? d_n_unsure : cscan + compact_scratch_words(b->n_pairs) - 1;
     HIP_TRY(ctx, filter_decide(b->n_pairs, b->d_win, b->n_reads, first, last, count, d_logits,
-                               fp->logit_lo, fp->logit_hi, d_keep, unsure, s));
+                               fp->logit_lo, fp->logit_hi, fp->logit_drop, d_keep, unsure, s));
     HIP_TRY(ctx, compact_pairs(b->n_pairs, d_keep, b->d_win, d_win_out, d_sel_ids, d_n_sel, cscan, s));
     return SW_OK;
 }

@@ -10,7 +10,8 @@
 // each with an 8192-bit prefilter bitmap indexed by the k-mer's first 6.5
 // bases.  The wave takes the read's candidate windows eight at a time and
 // treats their reference words (16 bases each) as one flat stream: lane l of
-// a 64-word chunk owns word l of the stream, whatever window it belongs to.  A
+// a 128-word chunk owns words l and l + 64 of the stream, whatever windows
+// they belong to.  A
 // lane forms the 16 k-mers that start in its word with shifts of the word
 // pair and tests them against the bitmap (five VALU operations each).  The
 // bitmap hits of the whole chunk (true seed matches plus about 1.5 % false
@@ -113,12 +114,17 @@ __device__ __forceinline__ uint32_t bin16(uint32_t x, float r)
     return (uint32_t)__builtin_fmaf((float)x, r, r * 0.03125f);
 }
 
+// maximum over the wave: a max-scan inside each 16-lane row, then the row
+// results combined with row broadcasts; lane 63 ends with the total
 __device__ __forceinline__ uint32_t wave_max(uint32_t v)
 {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1)
-        v = max(v, (uint32_t)__shfl_xor((int)v, off));
-    return v;
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true));   // row_shr:1
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true));   // row_shr:2
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true));   // row_shr:4
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true));   // row_shr:8
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, const uint32_t *first,
@@ -287,78 +293,97 @@ __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, con
                 L.cwo[0] = 0;
             lds_fence();
             const uint32_t total = L.cwo[Gn];
-            uint32_t c = 0, u0 = 0, u1 = 0;
-            // window of stream word wn (c only moves forward) and the word pair at it
-            auto fetch = [&](uint32_t wn) {
+            // Each lane owns two stream words per step (a 128-word chunk): c is the
+            // window of the lane's latest fetched word and only moves forward.
+            uint32_t c = 0;
+            auto fetch = [&](uint32_t wn, uint32_t &cw, uint32_t &x0, uint32_t &x1) {
                 while (c + 1 < (uint32_t)Gn && L.cwo[c + 1] <= wn)
                     ++c;
+                cw = c;
                 const uint64_t gw = (uint64_t)(L.wrb[cg + c] >> 4) + (uint64_t)(wn - L.cwo[c]);
-                u0 = b.d_ref2b[min(gw, ref_words - 1)];
-                u1 = b.d_ref2b[min(gw + 1, ref_words - 1)];
+                x0 = b.d_ref2b[min(gw, ref_words - 1)];
+                x1 = b.d_ref2b[min(gw + 1, ref_words - 1)];
             };
-            if ((uint32_t)lane < total)
-                fetch(lane);
-            for (uint32_t W = 0; W < total; W += 64) {
-                const uint32_t wc = W + lane, cc = c, a0 = u0, a1 = u1;
-                if (wc + 64 < total)
-                    fetch(wc + 64);
-                uint32_t cand = 0, head = 0;
-                int j0 = 0;
-                if (wc < total) {
-                    const uint32_t ci = cg + cc;
-                    const uint32_t rb = L.wrb[ci];
-                    const int nf = L.wnf[ci];
-                    const int o = L.wst[ci] ? 1 : 0;
-                    const int J = max(nf - kK + 1, 0);
-                    j0 = 16 * (int)(wc - L.cwo[cc]) - (int)(rb & 15u);
-                    // positions i of this word with 0 <= j0 + i < J (k-mers), < nf (bases)
-                    const int lo = max(-j0, 0);
-                    const int hiJ = min(J - j0, 16), hiN = min(nf - j0, 16);
-                    const uint32_t vmask = hiJ > lo ? ((1u << hiJ) - 1u) & ~((1u << lo) - 1u) : 0u;
-                    const uint32_t gmask =
-                        hiN > lo ? (uint32_t)(((1ull << (2 * hiN)) - 1ull) & ~((1ull << (2 * lo)) - 1ull))
-                                 : 0u;
-                    const uint32_t g = __popc((a0 ^ (a0 >> 1)) & 0x55555555u & gmask);   // C = 01, G = 10
-                    if (g)
-                        atomicAdd(&L.acc[cc][kRowGc], g);
-                    const uint32_t bmo = (bm_wave | (uint32_t)(o * kBm)) * 4u;   // bytes, multiple of 1024
-                    const uint32_t x16 = __builtin_amdgcn_alignbit(a1, a0, 16);
+            // bitmap candidates of one word: positions i whose k-mer may occur in the query
+            auto scan = [&](uint32_t wc, uint32_t cc, uint32_t a0, uint32_t a1, uint32_t &cand,
+                            uint32_t &head, int &j0) {
+                const uint32_t ci = cg + cc;
+                const uint32_t rb = L.wrb[ci];
+                const int nf = L.wnf[ci];
+                const int o = L.wst[ci] ? 1 : 0;
+                const int J = max(nf - kK + 1, 0);
+                j0 = 16 * (int)(wc - L.cwo[cc]) - (int)(rb & 15u);
+                // positions i of this word with 0 <= j0 + i < J (k-mers), < nf (bases)
+                const int lo = max(-j0, 0);
+                const int hiJ = min(J - j0, 16), hiN = min(nf - j0, 16);
+                const uint32_t vmask = hiJ > lo ? ((1u << hiJ) - 1u) & ~((1u << lo) - 1u) : 0u;
+                const uint32_t gmask =
+                    hiN > lo ? (uint32_t)(((1ull << (2 * hiN)) - 1ull) & ~((1ull << (2 * lo)) - 1ull)) : 0u;
+                const uint32_t g = __popc((a0 ^ (a0 >> 1)) & 0x55555555u & gmask);   // C = 01, G = 10
+                if (g)
+                    atomicAdd(&L.acc[cc][kRowGc], g);
+                const uint32_t bmo = (bm_wave | (uint32_t)(o * kBm)) * 4u;   // bytes, multiple of 1024
+                const uint32_t x16 = __builtin_amdgcn_alignbit(a1, a0, 16);
+                uint32_t m = 0;
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        // bits 0..12 of the k-mer at position i
-                        const uint32_t s = i < 10 ? (a0 >> (2 * i)) : (x16 >> (2 * i - 16));
-                        const uint32_t word = *reinterpret_cast<const uint32_t *>(
-                            reinterpret_cast<const char *>(bm_all) + and_or_3fc(s >> 3, bmo));
-                        cand |= __builtin_amdgcn_ubfe(word, s, 1u) << i;
-                    }
-                    cand &= vmask;
-                    head = (cc | (uint32_t)o << 4) << 24;
+                for (int i = 0; i < 16; ++i) {
+                    // bits 0..12 of the k-mer at position i
+                    const uint32_t sh = i < 10 ? (a0 >> (2 * i)) : (x16 >> (2 * i - 16));
+                    const uint32_t word = *reinterpret_cast<const uint32_t *>(
+                        reinterpret_cast<const char *>(bm_all) + and_or_3fc(sh >> 3, bmo));
+                    m |= __builtin_amdgcn_ubfe(word, sh, 1u) << i;
                 }
+                cand = m & vmask;
+                head = (cc | (uint32_t)o << 4) << 24;
+            };
+            // list entries of one word's candidates with list index in [base, base + kList)
+            auto emit = [&](uint32_t cm, uint32_t head, int j0, uint32_t a0, uint32_t a1, uint32_t &o2,
+                            uint32_t base) {
+                while (cm) {
+                    if (o2 >= base + kList)
+                        return;
+                    const int i = __builtin_ctz(cm);
+                    cm &= cm - 1u;
+                    if (o2 >= base) {
+                        const uint32_t km = __builtin_amdgcn_alignbit(a1, a0, 2u * (uint32_t)i) & 0xFFFFFFu;
+                        L.list[o2 - base] = make_uint2(km | head, (uint32_t)(j0 + i));
+                    }
+                    ++o2;
+                }
+            };
+            uint32_t pca = 0, pa0 = 0, pa1 = 0, pcb = 0, pb0 = 0, pb1 = 0;
+            if ((uint32_t)lane < total)
+                fetch(lane, pca, pa0, pa1);
+            if ((uint32_t)lane + 64 < total)
+                fetch(lane + 64, pcb, pb0, pb1);
+            for (uint32_t W = 0; W < total; W += 128) {
+                const uint32_t wa = W + lane, wb = W + 64 + lane;
+                const uint32_t ca = pca, a0 = pa0, a1 = pa1, cb = pcb, b0 = pb0, b1 = pb1;
+                if (wa + 128 < total)
+                    fetch(wa + 128, pca, pa0, pa1);
+                if (wb + 128 < total)
+                    fetch(wb + 128, pcb, pb0, pb1);
+                uint32_t candA = 0, headA = 0, candB = 0, headB = 0;
+                int j0A = 0, j0B = 0;
+                if (wa < total)
+                    scan(wa, ca, a0, a1, candA, headA, j0A);
+                if (wb < total)
+                    scan(wb, cb, b0, b1, candB, headB, j0B);
                 // offsets of every lane's candidates in the chunk's list (prefix over the wave)
-                const uint32_t cnt = __popc(cand);
+                const uint32_t cnt = __popc(candA) + __popc(candB);
                 uint32_t off = 0, tot = 0;
 #pragma unroll
-                for (int bp = 0; bp < 5; ++bp) {
+                for (int bp = 0; bp < 6; ++bp) {
                     const uint64_t m = __ballot((cnt >> bp) & 1u);
                     off += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << bp;
                     tot += (uint32_t)__popcll(m) << bp;
                 }
                 for (uint32_t base = 0; base < tot; base += kList) {
-                    if (cand && off < base + kList && off + cnt > base) {
-                        uint32_t cm = cand, o2 = off;
-                        do {
-                            const int i = __builtin_ctz(cm);
-                            cm &= cm - 1u;
-                            if (o2 >= base + kList)
-                                break;
-                            if (o2 >= base) {
-                                const uint32_t km =
-                                    __builtin_amdgcn_alignbit(a1, a0, 2u * (uint32_t)i) & 0xFFFFFFu;
-                                L.list[o2 - base] = make_uint2(km | head, (uint32_t)(j0 + i));
-                            }
-                            ++o2;
-                        } while (cm);
+                    if (cnt && off < base + kList && off + cnt > base) {
+                        uint32_t o2 = off;
+                        emit(candA, headA, j0A, a0, a1, o2, base);
+                        emit(candB, headB, j0B, b0, b1, o2, base);
                     }
                     lds_fence();
                     // probe the listed k-mers, 64 at a time

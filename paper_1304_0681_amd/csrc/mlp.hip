@@ -430,7 +430,7 @@ __global__ void __launch_bounds__(256) k_seg_final(uint32_t n_reads, const uint3
 __global__ void __launch_bounds__(256) k_decide(uint32_t n_reads, const uint32_t *first,
                                                 const uint32_t *last, const uint32_t *count,
                                                 const float *logits, float lo, float hi,
-                                                uint8_t *keep, uint32_t *n_unsure)
+                                                float drop, uint8_t *keep, uint32_t *n_unsure)
 {
     const uint32_t r = blockIdx.x * 256 + threadIdx.x;
     if (r >= n_reads || count[r] == 0)
@@ -444,6 +444,11 @@ __global__ void __launch_bounds__(256) k_decide(uint32_t n_reads, const uint32_t
             const float z = logits[a + c];
             mx = fmaxf(mx, z);
             unsure |= (z >= lo && z < hi);
+        }
+        if (mx < drop) {       // predicted unmapped: no candidate is aligned
+            for (uint32_t c = 0; c < k; ++c)
+                keep[a + c] = 0;
+            return;
         }
         unsure |= mx < hi;
     }
@@ -696,11 +701,11 @@ hipError_t read_segments(uint32_t n_pairs, const uint32_t *d_n, const sw_window 
 
 hipError_t filter_decide(uint32_t n_pairs, const sw_window *win, uint32_t n_reads,
                          const uint32_t *first, const uint32_t *last, const uint32_t *count,
-                         const float *logits, float lo, float hi, uint8_t *keep,
+                         const float *logits, float lo, float hi, float drop, uint8_t *keep,
                          uint32_t *n_unsure, hipStream_t st)
 {
     hipLaunchKernelGGL(k_decide, dim3(blocks_for(n_reads)), dim3(256), 0, st, n_reads, first, last,
-                       count, logits, lo, hi, keep, n_unsure);
+                       count, logits, lo, hi, drop, keep, n_unsure);
     hipLaunchKernelGGL(k_keep_noncontig, dim3(blocks_for(n_pairs)), dim3(256), 0, st, n_pairs, win,
                        n_reads, first, last, count, keep);
     return hipGetLastError();

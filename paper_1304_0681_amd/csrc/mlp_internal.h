@@ -42,7 +42,7 @@ hipError_t read_segments(uint32_t n_pairs, const uint32_t *d_n, const sw_window 
                          hipStream_t st);
 hipError_t filter_decide(uint32_t n_pairs, const sw_window *win, uint32_t n_reads,
                          const uint32_t *first, const uint32_t *last, const uint32_t *count,
-                         const float *logits, float lo, float hi, uint8_t *keep,
+                         const float *logits, float lo, float hi, float drop, uint8_t *keep,
                          uint32_t *n_unsure, hipStream_t st);
 size_t compact_scratch_words(uint32_t n);
 hipError_t compact_pairs(uint32_t n, const uint8_t *keep, const sw_window *win, sw_window *wout,

@@ -104,15 +104,17 @@ def read_segments_host(read_id: np.ndarray):
     return starts, counts
 
 
-def filter_outcome(z, scores, best, read_id, lo, hi):
+def filter_outcome(z, scores, best, read_id, lo, hi, drop=float("-inf")):
     """Apply the decision rule on host arrays: returns (kept mask, hit per read,
-    unsure per read) where hit = the kept pairs contain a best-scoring pair."""
+    unsure per read) where hit = the kept pairs contain a best-scoring pair.
+    Reads whose best logit is below `drop` keep nothing (and are not unsure)."""
     starts, counts = read_segments_host(read_id)
     mx = np.maximum.reduceat(z, starts)
     band = np.add.reduceat(((z >= lo) & (z < hi)).astype(np.int64), starts) > 0
-    unsure = (mx < hi) | band
+    dropped = mx < drop
+    unsure = ((mx < hi) | band) & ~dropped
     un_pair = np.repeat(unsure, counts)
-    keep = un_pair | (z >= hi)
+    keep = (un_pair | (z >= hi)) & ~np.repeat(dropped, counts)
     is_best = scores == best[read_id]
     hit = np.add.reduceat((keep & is_best).astype(np.int64), starts) > 0
     return keep, hit, unsure
@@ -138,6 +140,46 @@ def calibrate(z, scores, best, read_id, target: float = 0.9995, gaps=(0.0, 0.5, 
     return best_cfg[1], best_cfg[2], best_cfg[3]
 
 
+def calibrate_output(z, scores, best, read_id, t_map: int, target: float = 0.9995,
+                     gaps=(0.0, 0.5, 1.0, 2.0, 4.0), n_grid: int = 120):
+    """Thresholds (drop, lo, hi) with the fewest kept pairs whose recall on the
+    aligner's output is at least `target`.
+
+    Only alignments scoring at least t_map become records (Sec. 2, stage E task
+    iv); the others leave their read unmapped.  Recall is therefore taken over
+    the mapped reads (plain best score >= t_map): a mapped read is recalled
+    when the filtered best score equals the plain one.  An unmapped read stays
+    unmapped whatever the filter keeps, so reads whose best logit is below
+    `drop` are not aligned at all.  For each (lo, hi) of the grid, `drop` is
+    the highest value whose extra misses keep the recall at the target."""
+    starts, counts = read_segments_host(read_id)
+    mx = np.maximum.reduceat(z, starts)
+    mapped = best >= t_map
+    n_map = max(int(mapped.sum()), 1)
+    need = int(np.ceil(target * n_map))
+    qs = np.quantile(z, np.linspace(0.5, 0.9995, n_grid))
+    best_cfg = None
+    for hi in qs:
+        for gap in gaps:
+            lo = hi - gap
+            keep, hit, _ = filter_outcome(z, scores, best, read_id, lo, hi)
+            hm = hit & mapped
+            slack = int(hm.sum()) - need
+            if slack < 0:
+                continue
+            mx_hm = np.sort(mx[hm])
+            drop = float(mx_hm[slack]) if slack < len(mx_hm) else float("inf")
+            drop = min(drop, float(lo))
+            dropped = mx < drop
+            k = int(keep[~np.repeat(dropped, counts)].sum())
+            if best_cfg is None or k < best_cfg[0]:
+                rec = float((hm & ~dropped).sum() / n_map)
+                best_cfg = (k, drop, float(lo), float(hi), rec)
+    if best_cfg is None:
+        return float("-inf"), float("-inf"), float("inf"), 1.0
+    return best_cfg[1:]
+
+
 class FilterBuffers:
     """Device buffers of the filtered pipeline for one batch size."""
 
@@ -156,12 +198,12 @@ class FilterBuffers:
 
 
 def filtered_pass(ctx, mlp, db: DeviceBatch, lo: float, hi: float, buf: FilterBuffers,
-                  scoring=SCORING):
+                  scoring=SCORING, drop: float = float("-inf")):
     """Features -> logits -> decision -> compaction -> SW on the kept pairs ->
     best hit per read; everything stays on the device."""
     buf.n_unsure.zero_()
     sw_filter_candidates(ctx, db, mlp, lo, hi, buf.feat, buf.logits, buf.keep, buf.win_out,
-                         buf.sel, buf.n_sel, buf.n_unsure)
+                         buf.sel, buf.n_sel, buf.n_unsure, logit_drop=drop)
     kept = db.view(buf.win_out, db.n_pairs, buf.n_sel)
     sw_batch_score(ctx, kept, scoring, 0, buf.hits)
     sw_best_per_read(ctx, kept, buf.hits, 0, buf.best_pair, buf.best_score)

@@ -204,4 +204,23 @@ def test_filter_end_to_end(ctx):
     assert recall == float(hit.mean())
     assert recall >= 0.995, recall
     assert keep.mean() < 0.5, keep.mean()
+    # output-level rule: reads predicted unmapped are not aligned at all
+    t_map = 100
+    drop, lo2, hi2, _ = tr.calibrate_output(z, sc, best, rid, t_map, target=0.999)
+    assert drop <= lo2 <= hi2
+    tr.filtered_pass(ctx, mlp, db_te, lo2, hi2, buf, drop=drop)
+    torch.cuda.synchronize()
+    keep2 = buf.keep.cpu().numpy().astype(bool)
+    exp_keep2, hit2, _ = tr.filter_outcome(buf.logits.cpu().numpy(), sc_t, best_t, rid_t, lo2, hi2, drop)
+    assert (keep2 == exp_keep2).all()
+    assert int(buf.n_sel.item()) == int(keep2.sum())
+    fbest2 = buf.best_score.cpu().numpy()
+    exp2 = np.full(b_te.n_reads, -1)
+    np.maximum.at(exp2, rid_t[keep2], sc_t[keep2])
+    assert (fbest2 == exp2).all()          # reads with nothing kept report -1 (unmapped)
+    mapped = best_t >= t_map
+    rec2 = float((fbest2[mapped] == best_t[mapped]).mean())
+    assert rec2 >= 0.995, rec2
+    assert (fbest2[~mapped] < t_map).all()
+    assert keep2.sum() < keep.sum()
     sw.sw_mlp_destroy(ctx, mlp)
