@@ -109,7 +109,10 @@ typedef struct {
 typedef struct {
     int32_t score, read_begin, read_end, ref_begin, ref_end;
     uint32_t n_ops;   /* CIGAR ops written for this pair */
-    uint32_t status;  /* bit0: ops truncated to ops_stride; bit1: invalid pair */
+    uint32_t status;  /* bit0: ops truncated to ops_stride; bit1: invalid pair
+                         (id >= n_pairs or read_id out of range); bit2: not
+                         aligned, traceback scratch too small (see
+                         SW_OPT_TB_SCRATCH_MB) */
 } sw_aln;
 
 #define SW_WANT_ENDS 1u
@@ -162,6 +165,23 @@ sw_status sw_best_per_read(sw_ctx *ctx, const sw_batch *batch, const sw_hit *d_h
 sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *batch, const sw_scoring *sc,
                              const uint32_t *d_pair_ids, uint32_t n_sel, sw_aln *d_aln,
                              uint32_t *d_ops, uint32_t ops_stride, void *stream);
+
+/* Graph capture (the orchestration of a batch without per-call launch cost).
+ * Every library call issued on `stream` between sw_graph_begin and
+ * sw_graph_end is recorded, not run; sw_graph_launch replays the recording on
+ * any stream, reading and writing the same device buffers.  The calls of the
+ * score / best-hit / traceback path (and sw_pack2b, sw_filter_candidates with
+ * a host pair count) need no host round trip, so they can be captured.  A call
+ * that would have to grow a scratch buffer during capture fails with
+ * SW_E_STATE: make the same calls once, uncaptured, before capturing.  The
+ * stream must be a created stream (not the null stream); phase timing must be
+ * off.  If a captured call fails, end the capture with sw_graph_end (which
+ * then returns an error too) before using the context again. */
+typedef struct sw_graph sw_graph;
+sw_status sw_graph_begin(sw_ctx *ctx, void *stream);
+sw_status sw_graph_end(sw_ctx *ctx, void *stream, sw_graph **out);
+sw_status sw_graph_launch(sw_ctx *ctx, const sw_graph *g, void *stream);
+sw_status sw_graph_destroy(sw_ctx *ctx, sw_graph *g);
 
 /* ---------------------------------------------------------------------------
  * Learned candidate filter.
@@ -250,9 +270,14 @@ sw_status sw_filter_candidates(sw_ctx *ctx, const sw_batch *batch, const sw_mlp 
  *   query of the class <= 32767 and mismatch <= 0); 0 forces int32.  Results
  *   are identical either way.
  * SW_OPT_BLOCKS_PER_CU: workgroups (4 waves each) per compute unit of the
- *   persistent scoring kernels, 1..64 (default 2). */
+ *   persistent scoring kernels, 1..64 (default 2).
+ * SW_OPT_TB_SCRATCH_MB: device scratch of sw_batch_traceback in MiB, 1..65536
+ *   (default 1024).  Each query-length class runs as many pairs at once as
+ *   their direction codes fit; a class whose single largest slot does not fit
+ *   marks its pairs with status bit 2 (score -1) instead of aligning them. */
 #define SW_OPT_INT16 1
 #define SW_OPT_BLOCKS_PER_CU 2
+#define SW_OPT_TB_SCRATCH_MB 3
 sw_status sw_ctx_set_option(sw_ctx *ctx, int option, int value);
 
 /* Phase timing of sw_batch_score, from HIP events recorded on the call's

@@ -21,6 +21,7 @@ SW_OK, SW_E_INVALID, SW_E_RANGE, SW_E_NOMEM, SW_E_DEVICE, SW_E_NODEVICE, SW_E_ST
 SW_WANT_ENDS = 1
 SW_OPT_INT16 = 1
 SW_OPT_BLOCKS_PER_CU = 2
+SW_OPT_TB_SCRATCH_MB = 3
 OP_NAMES = "MIDNS"
 
 HIT_DTYPE = np.dtype([("score", "<i4"), ("read_end", "<i4"), ("ref_end", "<i4")])
@@ -101,9 +102,14 @@ def lib() -> ctypes.CDLL:
         L.sw_mlp_labels.argtypes = [P, ctypes.POINTER(sw_batch), P, P, I32, P, P]
         L.sw_filter_candidates.argtypes = [P, ctypes.POINTER(sw_batch), P,
                                            ctypes.POINTER(sw_filter_params), P, P, P, P, P, P, P, P]
+        L.sw_graph_begin.argtypes = [P, P]
+        L.sw_graph_end.argtypes = [P, P, ctypes.POINTER(P)]
+        L.sw_graph_launch.argtypes = [P, P, P]
+        L.sw_graph_destroy.argtypes = [P, P]
         for f in ("sw_ctx_create", "sw_ctx_destroy", "sw_pack2b", "sw_batch_score",
                   "sw_best_per_read", "sw_batch_traceback", "sw_cigar_string",
                   "sw_timing_enable", "sw_timing_get", "sw_ctx_set_option", "sw_mlp_create",
+                  "sw_graph_begin", "sw_graph_end", "sw_graph_launch", "sw_graph_destroy",
                   "sw_mlp_destroy", "sw_mlp_set_params", "sw_mlp_get_params", "sw_features",
                   "sw_mlp_forward", "sw_mlp_grad", "sw_mlp_train_step", "sw_mlp_labels",
                   "sw_filter_candidates"):
@@ -113,6 +119,7 @@ def lib() -> ctypes.CDLL:
 
 
 def _stream_ptr(stream=None):
+    """A torch.cuda.Stream (default: torch's current stream) as a hipStream_t."""
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -233,6 +240,27 @@ def sw_filter_candidates(ctx, batch, mlp, logit_lo, logit_hi, d_feat, d_logits, 
                                            _ptr(d_n_unsure), _stream_ptr(stream)))
 
 
+def sw_graph_begin(ctx, stream):
+    """Start recording the library calls issued on `stream` (a torch.cuda.Stream
+    created by the caller, not the null stream)."""
+    _check(ctx, lib().sw_graph_begin(ctx, _stream_ptr(stream)))
+
+
+def sw_graph_end(ctx, stream):
+    """Stop recording; returns a replayable graph handle."""
+    g = ctypes.c_void_p()
+    _check(ctx, lib().sw_graph_end(ctx, _stream_ptr(stream), ctypes.byref(g)))
+    return g
+
+
+def sw_graph_launch(ctx, g, stream=None):
+    _check(ctx, lib().sw_graph_launch(ctx, g, _stream_ptr(stream)))
+
+
+def sw_graph_destroy(ctx, g):
+    _check(ctx, lib().sw_graph_destroy(ctx, g))
+
+
 def sw_cigar_string(ops) -> str:
     a = np.ascontiguousarray(ops, dtype=np.uint32)
     buf = ctypes.create_string_buffer(16 * len(a) + 1)
@@ -280,6 +308,8 @@ class DeviceBatch:
         self.win = torch.from_numpy(w.copy()).to(dev)
         self.n_reads = len(read_len)
         self.n_pairs = len(windows)
+        self.read_len_max = int(np.max(read_len, initial=0))
+        self.window_len_max = int(np.max(np.asarray(windows)["len"], initial=0)) if len(windows) else 0
         self.pack_reads(stream)
         self.c = sw_batch(_ptr(self.ref2b), self.ref_len, _ptr(self.reads2b), self.reads_len,
                           _ptr(self.read_off), _ptr(self.read_len), self.n_reads, _ptr(self.win),

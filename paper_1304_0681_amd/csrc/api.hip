@@ -37,10 +37,12 @@ struct sw_ctx {
     // best-per-read keys
     uint64_t *keys = nullptr;
     size_t keys_n = 0;
-    // traceback code slots
+    // traceback code slots: a fixed budget, sized once
     uint32_t *tb = nullptr;
     size_t tb_bytes = 0;
-    uint32_t *host_meta = nullptr;   // pinned: per-class segments and maxima
+    size_t tb_budget = 1ull << 30;
+    // inside sw_graph_begin / sw_graph_end: no allocation, no host synchronisation
+    bool capturing = false;
     // filter scratch: read segments (first, last, count) and compaction offsets
     uint32_t *seg = nullptr;
     size_t seg_bytes = 0;
@@ -52,6 +54,11 @@ struct sw_ctx {
     bool timed_call = false;
     int32_t class_path[kNumClasses] = {};
     hipEvent_t ev[2 + kNumClasses] = {};
+};
+
+struct sw_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
 };
 
 namespace {
@@ -116,6 +123,9 @@ sw_status ensure(sw_ctx *ctx, void **buf, size_t *have, size_t need)
 {
     if (*have >= need)
         return SW_OK;
+    if (ctx->capturing)
+        return fail(ctx, SW_E_STATE, "scratch of %zu bytes needed during graph capture: make the "
+                    "same calls once before capturing", need);
     const size_t old = *have;
     if (*buf)
         HIP_TRY(ctx, hipFree(*buf));
@@ -177,8 +187,7 @@ sw_status sw_ctx_create(int hip_device, sw_ctx **out)
         ctx->shapes[c] = kDefaultClasses[c];
         ctx->blocks_per_cu[c] = 2;
     }
-    if (hipSetDevice(hip_device) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void **>(&ctx->host_meta), 4 * 4 * kNumClasses) != hipSuccess) {
+    if (hipSetDevice(hip_device) != hipSuccess) {
         delete ctx;
         return fail(nullptr, SW_E_DEVICE, "device set-up failed");
     }
@@ -198,7 +207,6 @@ sw_status sw_ctx_destroy(sw_ctx *ctx)
     if (ctx->keys) keep(hipFree(ctx->keys));
     if (ctx->tb) keep(hipFree(ctx->tb));
     if (ctx->seg) keep(hipFree(ctx->seg));
-    if (ctx->host_meta) keep(hipHostFree(ctx->host_meta));
     for (auto &ev : ctx->ev)
         if (ev) keep(hipEventDestroy(ev));
     delete ctx;
@@ -250,6 +258,9 @@ sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
     // strip buffers only when some read may exceed the largest single-strip class
     const bool may_strip = b->reads_len > (uint64_t)kDefaultClasses[kNumClasses - 2].m_max;
     if (may_strip && !ctx->strip_buf) {
+        if (ctx->capturing)
+            return fail(ctx, SW_E_STATE, "strip buffers needed during graph capture: make the same "
+                        "calls once before capturing");
         ctx->strip_waves = 64;
         HIP_TRY(ctx, hipMalloc(reinterpret_cast<void **>(&ctx->strip_buf),
                                sizeof(int2) * 65536ull * (size_t)ctx->strip_waves));
@@ -360,40 +371,87 @@ sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *b, const sw_scoring *s
     if ((st = bucket_scratch(ctx, n_sel, &bs)))
         return st;
     HIP_TRY(ctx, launch_bucket(*b, d_pair_ids, n_sel, bs, nullptr, d_aln, s));
-    // size the code slots from the per-class maxima (one stream synchronisation)
-    uint32_t *meta = ctx->host_meta;
-    HIP_TRY(ctx, hipMemcpyAsync(meta, bs.seg, 4 * 2 * kNumClasses, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipMemcpyAsync(meta + 2 * kNumClasses, bs.maxlen, 4 * 2 * kNumClasses,
-                                hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
+    // Code slots come from a fixed scratch budget; every class kernel sizes its
+    // slots from the class maxima on the device and runs the waves that fit, so
+    // the call needs no host round trip and can be captured in a graph.
+    void *buf = ctx->tb;
+    size_t have = ctx->tb_bytes;
+    if ((st = ensure(ctx, &buf, &have, ctx->tb_budget)))
+        return st;
+    ctx->tb = static_cast<uint32_t *>(buf);
+    ctx->tb_bytes = have;
+    const int wpb = traceback_waves_per_block();
+    const int grid = std::max(1, ctx->n_cu * 8 / wpb);
     for (int c = 0; c < kNumClasses; ++c) {
-        const uint32_t count = meta[2 * c + 1] - meta[2 * c];
-        if (count == 0)
-            continue;
-        const uint64_t nmax = meta[2 * kNumClasses + c];
-        const uint64_t mmax = meta[3 * kNumClasses + c];
-        const uint64_t sr = (uint64_t)traceback_rows_cap(c);
-        const bool strip = c == kNumClasses - 1;
-        const uint64_t rows_cap = strip ? (mmax + sr - 1) / sr * sr : sr;
-        const uint64_t slot_words = rows_cap / 8 * nmax + (strip ? 2 * nmax : 0) + mmax + nmax + 8;
-        const int ppw = traceback_pairs_per_wave(c);
-        const int wpb = traceback_waves_per_block();
-        uint64_t waves = std::min<uint64_t>((count + ppw - 1) / ppw, (uint64_t)ctx->n_cu * 8);
-        const uint64_t budget = 4ull << 30;   // bytes of code slots at most
-        while (waves > (uint64_t)wpb && waves * ppw * slot_words * 4 > budget)
-            waves /= 2;
-        const uint64_t blocks = (waves + wpb - 1) / wpb;
-        const uint64_t need = blocks * wpb * ppw * slot_words * 4;
-        void *buf = ctx->tb;
-        size_t have = ctx->tb_bytes;
-        if ((st = ensure(ctx, &buf, &have, need)))
-            return st;
-        ctx->tb = static_cast<uint32_t *>(buf);
-        ctx->tb_bytes = have;
+        if (c > 0 && (uint64_t)kDefaultClasses[c - 1].m_max >= b->reads_len)
+            continue;   // no read of this batch can fall in this class
         HIP_TRY(ctx, launch_traceback_class(c, *b, *sc, d_pair_ids, bs.ids, bs.seg, bs.counter,
-                                            d_aln, d_ops, ops_stride, ctx->tb, slot_words,
-                                            (int)blocks, s));
+                                            d_aln, d_ops, ops_stride, ctx->tb,
+                                            std::min(ctx->tb_bytes, ctx->tb_budget) / 4, bs.maxlen,
+                                            grid, s));
     }
+    return SW_OK;
+}
+
+sw_status sw_graph_begin(sw_ctx *ctx, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    if (!stream)
+        return fail(ctx, SW_E_INVALID, "graph capture needs a created stream, not the null stream");
+    if (ctx->capturing)
+        return fail(ctx, SW_E_STATE, "a capture is already open on this context");
+    if (ctx->timing)
+        return fail(ctx, SW_E_STATE, "disable phase timing before capturing");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal));
+    ctx->capturing = true;
+    return SW_OK;
+}
+
+sw_status sw_graph_end(sw_ctx *ctx, void *stream, sw_graph **out)
+{
+    if (!ctx || !out)
+        return fail(ctx, SW_E_INVALID, "NULL argument");
+    if (!ctx->capturing)
+        return fail(ctx, SW_E_STATE, "no capture is open on this context");
+    ctx->capturing = false;
+    *out = nullptr;
+    hipGraph_t g = nullptr;
+    HIP_TRY(ctx, hipStreamEndCapture(static_cast<hipStream_t>(stream), &g));
+    hipGraphExec_t x = nullptr;
+    const hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return fail(ctx, SW_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    *out = new sw_graph{g, x};
+    return SW_OK;
+}
+
+sw_status sw_graph_launch(sw_ctx *ctx, const sw_graph *g, void *stream)
+{
+    if (!ctx || !g)
+        return fail(ctx, SW_E_INVALID, "NULL argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_graph_destroy(sw_ctx *ctx, sw_graph *g)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    if (!g)
+        return SW_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipError_t e = hipGraphExecDestroy(g->exec);
+    const hipError_t e2 = hipGraphDestroy(g->graph);
+    delete g;
+    if (e == hipSuccess)
+        e = e2;
+    if (e != hipSuccess)
+        return fail(ctx, SW_E_DEVICE, "sw_graph_destroy: %s", hipGetErrorString(e));
     return SW_OK;
 }
 
@@ -410,6 +468,11 @@ sw_status sw_ctx_set_option(sw_ctx *ctx, int option, int value)
             return fail(ctx, SW_E_RANGE, "blocks per CU must be in [1, 64]");
         for (int c = 0; c < kNumClasses; ++c)
             ctx->blocks_per_cu[c] = value;
+        return SW_OK;
+    case SW_OPT_TB_SCRATCH_MB:
+        if (value < 1 || value > 65536)
+            return fail(ctx, SW_E_RANGE, "traceback scratch must be in [1, 65536] MiB");
+        ctx->tb_budget = (size_t)value << 20;
         return SW_OK;
     default:
         return fail(ctx, SW_E_INVALID, "unknown option %d", option);

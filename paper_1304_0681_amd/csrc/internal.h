@@ -79,7 +79,7 @@ int traceback_waves_per_block();
 hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &sc,
                                   const uint32_t *sel, const uint32_t *ids, const uint32_t *seg,
                                   uint32_t *counter, sw_aln *aln, uint32_t *ops,
-                                  uint32_t ops_stride, uint32_t *codes, uint64_t slot_words,
-                                  int grid, hipStream_t st);
+                                  uint32_t ops_stride, uint32_t *codes, uint64_t codes_words,
+                                  const uint32_t *maxlen, int grid, hipStream_t st);
 
 }  // namespace hpgsw

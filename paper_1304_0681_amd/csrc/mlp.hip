@@ -463,6 +463,12 @@ __global__ void __launch_bounds__(256) k_decide(uint32_t n_reads, const uint32_t
         keep[a + c] = logits[a + c] >= hi ? 1 : 0;
 }
 
+__global__ void k_zero_count(uint32_t *p)
+{
+    if (threadIdx.x == 0)
+        *p = 0;
+}
+
 // non-contiguous reads: keep every pair of those reads
 __global__ void __launch_bounds__(256) k_keep_noncontig(uint32_t n_pairs, const sw_window *win,
                                                         uint32_t n_reads, const uint32_t *first,
@@ -717,8 +723,10 @@ hipError_t compact_pairs(uint32_t n, const uint8_t *keep, const sw_window *win, 
                          uint32_t *ids_out, uint32_t *d_n_out, uint32_t *scratch, hipStream_t st)
 {
     const uint32_t nb = (n + kScanItems - 1) / kScanItems;
-    if (nb == 0)
-        return hipMemsetAsync(d_n_out, 0, 4, st);
+    if (nb == 0) {      // a kernel, not a memset node, so that the call can be captured
+        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, st, d_n_out);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_block_count, dim3(nb), dim3(256), 0, st, n, keep, scratch);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, nb, scratch, d_n_out);
     hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, st, n, keep, scratch, win, wout, ids_out);

@@ -37,8 +37,9 @@ struct TBParams {
     sw_aln *aln;
     uint32_t *ops;
     uint32_t ops_stride;
-    uint32_t *codes;           // scratch: per group slot
-    uint64_t slot_words;       // words per group slot
+    uint32_t *codes;           // scratch holding one slot per pair in flight
+    uint64_t codes_words;      // size of the scratch in 32-bit words
+    const uint32_t *maxlen;    // per class: longest window, then longest read
 };
 
 template <int G>
@@ -100,7 +101,18 @@ __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
     const uint32_t n_tasks = (seg_end - seg_begin + PPW - 1) / PPW;
     const int go = P.go, ge = P.ge;
     const uint32_t wave_global = blockIdx.x * kWaves + (threadIdx.x >> 6);
-    uint32_t *slot_codes = P.codes + (uint64_t)(wave_global * PPW + grp) * P.slot_words;
+    // Slot size from the class maxima (read on the device, so no host round
+    // trip): codes of every column, the strip boundary row, and the op runs.
+    // Waves whose slots do not fit the scratch take no work; with no room for
+    // even one wave every pair of the class is marked and skipped.
+    const uint64_t nmax = P.maxlen[P.cls], mmax = P.maxlen[kNumClasses + P.cls];
+    const uint64_t rows_max = STRIP ? (mmax + SR - 1) / SR * SR : (uint64_t)SR;
+    const uint64_t slot_words = rows_max / 8 * nmax + (STRIP ? 2 * nmax : 0) + mmax + nmax + 8;
+    const uint64_t fit = P.codes_words / ((uint64_t)PPW * slot_words);
+    const bool no_room = fit == 0;
+    if (!no_room && wave_global >= fit)
+        return;
+    uint32_t *slot_codes = P.codes + (no_room ? 0 : (uint64_t)(wave_global * PPW + grp) * slot_words);
 
     for (;;) {
         uint32_t task = 0;
@@ -112,6 +124,11 @@ __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
         const uint32_t slot = seg_begin + task * PPW + grp;
         const bool active = slot < seg_end;
         const uint32_t k_sel = active ? P.ids[slot] : 0u;
+        if (no_room) {        // wave-uniform
+            if (active && first)
+                P.aln[k_sel] = sw_aln{-1, -1, -1, -1, -1, 0u, 4u};
+            continue;
+        }
         const uint32_t pair = P.sel[k_sel];
         const sw_window w = P.win[pair];
         int m = 0, n = 0;
@@ -360,8 +377,8 @@ int traceback_waves_per_block() { return kWaves; }
 hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &sc,
                                   const uint32_t *sel, const uint32_t *ids, const uint32_t *seg,
                                   uint32_t *counter, sw_aln *aln, uint32_t *ops,
-                                  uint32_t ops_stride, uint32_t *codes, uint64_t slot_words,
-                                  int grid, hipStream_t st)
+                                  uint32_t ops_stride, uint32_t *codes, uint64_t codes_words,
+                                  const uint32_t *maxlen, int grid, hipStream_t st)
 {
     TBParams p;
     p.ref = b.d_ref2b;
@@ -385,7 +402,8 @@ hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &
     p.ops = ops;
     p.ops_stride = ops_stride;
     p.codes = codes;
-    p.slot_words = slot_words;
+    p.codes_words = codes_words;
+    p.maxlen = maxlen;
     switch (cls) {
     case 0: return tb_launch<2, 8, false>(p, grid, st);
     case 1: return tb_launch<2, 16, false>(p, grid, st);
