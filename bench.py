@@ -223,6 +223,76 @@ def bench_filter(ctx, args):
     }
 
 
+def bench_spliced(ctx, args):
+    """Spliced long-read seeds: score every (seed, window) pair, best window per
+    seed, traceback to CIGAR; the whole pass replayed as one captured graph."""
+    import torch
+
+    import paper_1304_0681_amd as sw
+    import synth
+    from paper_1304_0681_amd.pipeline import AlignPass
+
+    t0 = time.perf_counter()
+    b = synth.spliced(n_reads=args.spliced_reads)
+    t_gen = time.perf_counter() - t0
+    db = sw.DeviceBatch.from_synth(ctx, b)
+    ap = AlignPass(ctx, db, SCORING)
+    s = torch.cuda.Stream()
+    ap.capture(s)
+    # eager pass with events between its phases (same stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    phase = np.zeros(3)
+    for rep in range(args.warmup + args.steps):
+        with torch.cuda.stream(s):
+            ev[0].record(s)
+            db.pack_reads(s)
+            sw.sw_batch_score(ctx, db, SCORING, 0, ap.hits, s)
+            ev[1].record(s)
+            sw.sw_best_per_read(ctx, db, ap.hits, 0, ap.best_pair, ap.best_score, ap.mapped, s)
+            ev[2].record(s)
+            sw.sw_batch_traceback(ctx, db, SCORING, ap.best_pair, db.n_reads, ap.aln, ap.ops,
+                                  ap.ops_stride, s)
+            ev[3].record(s)
+        s.synchronize()
+        if rep >= args.warmup:
+            phase += [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+    phase /= args.steps
+    # graph replays: the timed form
+    for _ in range(args.warmup):
+        ap.replay(s)
+    s.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        ap.replay(s)
+    s.synchronize()
+    t_step = (time.perf_counter() - t1) / args.steps
+    bp = ap.best_pair.cpu().numpy().view(np.uint32)
+    aln = sw.aln_to_numpy(ap.aln)
+    ok = bp < b.n_pairs
+    m = b.read_len[b.windows["read_id"][bp[ok]]].astype(np.int64)
+    n = np.minimum(b.windows["len"][bp[ok]].astype(np.int64),
+                   len(b.ref) - b.windows["ref_begin"][bp[ok]].astype(np.int64))
+    tb_cells = int((m * n).sum())
+    cells = b.cells()
+    ap.close()
+    return {
+        "workload": f"spliced long reads: {args.spliced_reads} reads of 400-800 nt (2-4 exons, "
+                    f"introns 50-5000 nt, 16 Mb reference) split into 100-nt seeds, 4-12 windows "
+                    f"of 200-1000 nt per seed; score all, traceback of the best window per seed",
+        "reads": args.spliced_reads, "seeds": b.n_reads, "pairs": b.n_pairs, "cells": cells,
+        "graph_ms_per_step": round(t_step * 1e3, 3),
+        "reads_per_s": round(args.spliced_reads / t_step, 1),
+        "seeds_per_s": round(b.n_reads / t_step, 1),
+        "gcups_score": round(cells / t_step / 1e9, 1),
+        "eager_phase_ms": {"encode_bucket_score": round(phase[0], 3), "best_hit": round(phase[1], 3),
+                           "traceback": round(phase[2], 3)},
+        "traceback_cells": tb_cells,
+        "traceback_gcups": round(tb_cells / (phase[2] / 1e3) / 1e9, 1),
+        "seeds_aligned": int(np.count_nonzero(aln["score"] > 0)),
+        "generation_seconds": round(t_gen, 1),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +306,9 @@ def main():
     ap.add_argument("--no-filter", action="store_true", help="skip the learned-filter comparison")
     ap.add_argument("--filter-reads", type=int, default=1_000_000)
     ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
+    ap.add_argument("--no-spliced", action="store_true", help="skip the spliced-seed traceback pass")
+    ap.add_argument("--spliced-reads", type=int, default=200_000)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -257,6 +330,15 @@ def main():
         f"(generated in {time.perf_counter() - t:.1f} s)")
 
     ctx = sw.sw_ctx_create(0)
+    tune = None
+    if not args.no_autotune:
+        # tile shapes and workgroups per CU tuned on a separate sample of the workload
+        sample = synth.config2(n_reads=200_000, seed=synth.BASE_SEED + 42)
+        dbs = sw.DeviceBatch.from_synth(ctx, sample)
+        tune = [t for t in sw.sw_autotune(ctx, dbs, SCORING, 0, repeats=3) if t["path"]]
+        del dbs, sample
+        log("autotune: " + "; ".join(f"m<={t['m_max']}: {t['G']}x{t['RPL']} bpc {t['blocks_per_cu']} "
+                                     f"{t['ms']:.2f} ms (default {t['ms_default']:.2f})" for t in tune))
     db = sw.DeviceBatch.from_synth(ctx, b)
     hits = torch.empty((b.n_pairs, 3), dtype=torch.int32, device="cuda")
     best_pair = torch.empty(b.n_reads, dtype=torch.int32, device="cuda")
@@ -336,9 +418,17 @@ def main():
             "frac_of_int32_roofline": round(kern_gcups / PEAK_GCUPS_INT32, 4),
         },
     }
+    if tune is not None:
+        out["autotune"] = [{"m_max": t["m_max"], "tile": [t["G"], t["RPL"]],
+                            "blocks_per_cu": t["blocks_per_cu"], "path": PATHS.get(t["path"], "int32"),
+                            "ms": round(t["ms"], 3), "ms_default": round(t["ms_default"], 3)}
+                           for t in tune]
+    del db, hits
     if not args.no_filter:
-        del db, hits
         out["filter"] = bench_filter(ctx, args)
+    if not args.no_spliced:
+        log("spliced seeds ...")
+        out["spliced"] = bench_spliced(ctx, args)
     sw.sw_ctx_destroy(ctx)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

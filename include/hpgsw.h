@@ -278,6 +278,34 @@ sw_status sw_filter_candidates(sw_ctx *ctx, const sw_batch *batch, const sw_mlp 
 #define SW_OPT_INT16 1
 #define SW_OPT_BLOCKS_PER_CU 2
 #define SW_OPT_TB_SCRATCH_MB 3
+
+/* Autotuning of the score kernels (the batching pattern's tile shapes).
+ * Pairs are bucketed by query length into SW_NUM_CLASSES classes (upper
+ * bounds 16, 32, 64, 100, 128, 160, 256, 512, 1024, 2048 and 65535 bases); each
+ * class runs a persistent kernel whose tile is G lanes per pair x RPL query
+ * rows per lane (G * RPL >= the class bound; the last class walks the query in
+ * strips of 64 x 32 rows).  sw_autotune times, on the caller's sample batch,
+ * every candidate (tile shape, workgroups per compute unit) of every class the
+ * sample populates, `repeats` calls each with HIP events around each class's
+ * kernel, and keeps the fastest per class in ctx for later sw_batch_score
+ * calls (classes the sample leaves empty keep their defaults, path 0).
+ * Candidate shapes for a class are the default shapes of that class and
+ * of the next two (all exercised by the parity tests); workgroups per compute
+ * unit are 1, 2 or 4.  Results are identical for every candidate: only time
+ * changes.  out[SW_NUM_CLASSES] (host, may be NULL) receives the choice.
+ * Synchronises the stream; not capturable; allocates a temporary hit buffer. */
+#define SW_NUM_CLASSES 11
+typedef struct {
+    int32_t m_max;          /* query-length bound of the class */
+    int32_t G, RPL;         /* chosen tile: lanes per pair, rows per lane */
+    int32_t blocks_per_cu;  /* chosen workgroups (4 waves) per compute unit */
+    int32_t path;           /* 0 class not run, 1 int32, 2 int32 with ends, 3 packed int16 */
+    int32_t candidates;     /* candidates timed */
+    float ms;               /* best time of the class per call (0 if not run) */
+    float ms_default;       /* time of the default choice per call */
+} sw_tune_entry;
+sw_status sw_autotune(sw_ctx *ctx, const sw_batch *sample, const sw_scoring *sc, uint32_t flags,
+                      int repeats, sw_tune_entry *out, void *stream);
 sw_status sw_ctx_set_option(sw_ctx *ctx, int option, int value);
 
 /* Phase timing of sw_batch_score, from HIP events recorded on the call's

@@ -102,6 +102,8 @@ def lib() -> ctypes.CDLL:
         L.sw_mlp_labels.argtypes = [P, ctypes.POINTER(sw_batch), P, P, I32, P, P]
         L.sw_filter_candidates.argtypes = [P, ctypes.POINTER(sw_batch), P,
                                            ctypes.POINTER(sw_filter_params), P, P, P, P, P, P, P, P]
+        L.sw_autotune.argtypes = [P, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scoring), U32,
+                                  ctypes.c_int, P, P]
         L.sw_graph_begin.argtypes = [P, P]
         L.sw_graph_end.argtypes = [P, P, ctypes.POINTER(P)]
         L.sw_graph_launch.argtypes = [P, P, P]
@@ -110,6 +112,7 @@ def lib() -> ctypes.CDLL:
                   "sw_best_per_read", "sw_batch_traceback", "sw_cigar_string",
                   "sw_timing_enable", "sw_timing_get", "sw_ctx_set_option", "sw_mlp_create",
                   "sw_graph_begin", "sw_graph_end", "sw_graph_launch", "sw_graph_destroy",
+                  "sw_autotune",
                   "sw_mlp_destroy", "sw_mlp_set_params", "sw_mlp_get_params", "sw_features",
                   "sw_mlp_forward", "sw_mlp_grad", "sw_mlp_train_step", "sw_mlp_labels",
                   "sw_filter_candidates"):
@@ -238,6 +241,25 @@ def sw_filter_candidates(ctx, batch, mlp, logit_lo, logit_hi, d_feat, d_logits, 
                                            _ptr(d_feat), _ptr(d_logits), _ptr(d_keep),
                                            _ptr(d_win_out), _ptr(d_sel_ids), _ptr(d_n_sel),
                                            _ptr(d_n_unsure), _stream_ptr(stream)))
+
+
+SW_NUM_CLASSES = 11
+
+
+class sw_tune_entry(ctypes.Structure):
+    _fields_ = [("m_max", ctypes.c_int32), ("G", ctypes.c_int32), ("RPL", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("ms", ctypes.c_float), ("ms_default", ctypes.c_float)]
+
+
+def sw_autotune(ctx, batch, scoring, flags=0, repeats=3, stream=None):
+    """Tune the score kernels on a sample batch (kept in ctx); returns one dict per
+    query-length class."""
+    out = (sw_tune_entry * SW_NUM_CLASSES)()
+    _check(ctx, lib().sw_autotune(ctx, ctypes.byref(batch.c), ctypes.byref(_sc(scoring)),
+                                  int(flags), int(repeats), ctypes.cast(out, ctypes.c_void_p),
+                                  _stream_ptr(stream)))
+    return [{f: getattr(e, f) for f, _ in sw_tune_entry._fields_} for e in out]
 
 
 def sw_graph_begin(ctx, stream):

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 #include "mlp_internal.h"
@@ -17,8 +18,9 @@ const ClassShape kDefaultClasses[kNumClasses] = {
 
 int score_class_m_max(int cls) { return kDefaultClasses[cls].m_max; }
 
-// Packed int16 shapes enabled for dispatch.
-static bool packed_verified(const ClassShape &s) { return s.G == 4 && s.RPL == 25; }
+// Packed int16 is dispatched only for the class and shape it is verified on
+// (queries of 65-100 bases, 4 lanes x 25 rows).
+static bool packed_verified(int cls, const ClassShape &s) { return cls == 3 && s.G == 4 && s.RPL == 25; }
 
 }  // namespace hpgsw
 
@@ -310,7 +312,7 @@ sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
         // kernel for all classes did not return, and its cause is not known.
         const bool packed = mode == 0 && ctx->int16 && !strip && sc->mismatch <= 0 &&
                             (int64_t)sc->match * kDefaultClasses[c].m_max <= 32767 &&
-                            packed_verified(ctx->shapes[c]);
+                            packed_verified(c, ctx->shapes[c]);
         if (packed)
             HIP_TRY(ctx, launch_score16_class(ctx->shapes[c].G, ctx->shapes[c].RPL, p, grid, s));
         else
@@ -422,7 +424,7 @@ sw_status sw_graph_end(sw_ctx *ctx, void *stream, sw_graph **out)
     hipGraphExec_t x = nullptr;
     const hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         return fail(ctx, SW_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
     *out = new sw_graph{g, x};
@@ -506,6 +508,166 @@ sw_status sw_timing_get(sw_ctx *ctx, sw_timing *out)
         out->score_ms += out->class_ms[c];
         out->class_path[c] = ctx->class_path[c];
     }
+    return SW_OK;
+}
+
+sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint32_t flags,
+                      int repeats, sw_tune_entry *out, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    sw_status st = check_batch(ctx, b);
+    if (st)
+        return st;
+    if ((st = check_scoring(ctx, sc)))
+        return st;
+    if (repeats < 1 || repeats > 100)
+        return fail(ctx, SW_E_RANGE, "repeats must be in [1, 100]");
+    if (ctx->capturing)
+        return fail(ctx, SW_E_STATE, "sw_autotune cannot be captured");
+    static_assert(SW_NUM_CLASSES == kNumClasses, "class count of the ABI");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    // candidates: default shapes of the class and the next two (rows cover the
+    // class), each at 1, 2 and 4 workgroups per compute unit
+    struct Cand {
+        ClassShape shape;
+        int bpc;
+    };
+    std::vector<Cand> cand[kNumClasses];
+    const int bpcs[3] = {1, 2, 4};
+    for (int c = 0; c < kNumClasses; ++c) {
+        std::vector<ClassShape> shapes;
+        const int last = c == kNumClasses - 1 ? c : std::min(c + 2, kNumClasses - 2);
+        for (int d = c; d <= last; ++d) {
+            ClassShape sh = kDefaultClasses[d];
+            sh.m_max = kDefaultClasses[c].m_max;
+            bool dup = false;
+            for (const ClassShape &o : shapes)
+                dup |= o.G == sh.G && o.RPL == sh.RPL;
+            if (!dup)
+                shapes.push_back(sh);
+        }
+        for (const ClassShape &sh : shapes)
+            for (int bpc : bpcs)
+                cand[c].push_back(Cand{sh, bpc});
+    }
+    size_t K = 0;
+    for (auto &v : cand)
+        K = std::max(K, v.size());
+    ClassShape keep_shapes[kNumClasses];
+    int keep_bpc[kNumClasses];
+    memcpy(keep_shapes, ctx->shapes, sizeof keep_shapes);
+    memcpy(keep_bpc, ctx->blocks_per_cu, sizeof keep_bpc);
+    const bool was_timing = ctx->timing;
+    void *hits = nullptr;
+    auto restore = [&]() {
+        if (hits)
+            (void)hipFree(hits);
+        ctx->timing = was_timing;
+        ctx->timed_call = false;
+    };
+    if (b->n_pairs) {
+        const hipError_t e = hipMalloc(&hits, sizeof(sw_hit) * (size_t)b->n_pairs);
+        if (e != hipSuccess) {
+            restore();
+            return fail(ctx, SW_E_NOMEM, "sw_autotune: %s", hipGetErrorString(e));
+        }
+    }
+    if ((st = sw_timing_enable(ctx, 1))) {
+        restore();
+        return st;
+    }
+    uint32_t seg[2 * kNumClasses] = {};
+    float best_ms[kNumClasses], def_ms[kNumClasses];
+    int best_k[kNumClasses], best_path[kNumClasses], def_path[kNumClasses];
+    for (int c = 0; c < kNumClasses; ++c) {
+        best_ms[c] = 0.f;
+        def_ms[c] = 0.f;
+        best_k[c] = -1;
+        best_path[c] = 0;
+        def_path[c] = 0;
+    }
+    // k = -1: the defaults (also warms every kernel up)
+    for (int k = -1; k < (int)K && b->n_pairs; ++k) {
+        for (int c = 0; c < kNumClasses; ++c) {
+            if (k < 0) {
+                ctx->shapes[c] = kDefaultClasses[c];
+                ctx->blocks_per_cu[c] = 2;
+            } else {
+                const Cand &x = cand[c][std::min<size_t>((size_t)k, cand[c].size() - 1)];
+                ctx->shapes[c] = x.shape;
+                ctx->blocks_per_cu[c] = x.bpc;
+            }
+        }
+        float acc[kNumClasses] = {};
+        int path[kNumClasses] = {};
+        for (int rep = 0; rep < repeats + (k < 0 ? 1 : 0); ++rep) {
+            sw_timing t;
+            if ((st = sw_batch_score(ctx, b, sc, flags, static_cast<sw_hit *>(hits), stream)) ||
+                (st = sw_timing_get(ctx, &t))) {
+                memcpy(ctx->shapes, keep_shapes, sizeof keep_shapes);
+                memcpy(ctx->blocks_per_cu, keep_bpc, sizeof keep_bpc);
+                restore();
+                return st;
+            }
+            if (k < 0 && rep == 0) {   // warm-up; read how many pairs each class holds
+                BucketScratch bs;
+                if ((st = bucket_scratch(ctx, b->n_pairs, &bs))) {
+                    restore();
+                    return st;
+                }
+                const hipError_t e = hipMemcpy(seg, bs.seg, sizeof seg, hipMemcpyDeviceToHost);
+                if (e != hipSuccess) {
+                    restore();
+                    return fail(ctx, SW_E_DEVICE, "sw_autotune: %s", hipGetErrorString(e));
+                }
+                continue;
+            }
+            for (int c = 0; c < kNumClasses; ++c) {
+                acc[c] += t.class_ms[c] / repeats;
+                path[c] = t.class_path[c];
+            }
+        }
+        for (int c = 0; c < kNumClasses; ++c) {
+            if (k < 0) {
+                def_ms[c] = acc[c];
+                def_path[c] = path[c];
+            } else if ((size_t)k < cand[c].size() && (best_k[c] < 0 || acc[c] < best_ms[c])) {
+                best_ms[c] = acc[c];
+                best_k[c] = k;
+                best_path[c] = path[c];
+            }
+        }
+    }
+    // keep the fastest candidate per class (the default if it was not beaten)
+    for (int c = 0; c < kNumClasses; ++c) {
+        ClassShape sh = kDefaultClasses[c];
+        int bpc = 2;
+        float ms = def_ms[c];
+        const bool populated = seg[2 * c + 1] > seg[2 * c];
+        int pth = populated ? def_path[c] : 0;
+        if (populated && best_k[c] >= 0 && best_ms[c] < def_ms[c]) {
+            sh = cand[c][best_k[c]].shape;
+            bpc = cand[c][best_k[c]].bpc;
+            ms = best_ms[c];
+            pth = best_path[c];
+        }
+        ctx->shapes[c] = sh;
+        ctx->blocks_per_cu[c] = bpc;
+        if (out) {
+            out[c].m_max = kDefaultClasses[c].m_max;
+            out[c].G = sh.G;
+            out[c].RPL = sh.RPL;
+            out[c].blocks_per_cu = bpc;
+            out[c].path = pth;
+            out[c].candidates = (int32_t)cand[c].size();
+            out[c].ms = pth ? ms : 0.f;
+            out[c].ms_default = pth ? def_ms[c] : 0.f;
+        }
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    restore();
     return SW_OK;
 }
 
