@@ -293,6 +293,103 @@ def bench_spliced(ctx, args):
     }
 
 
+def bench_stream(ctx, args):
+    """Paired 150-nt mates against a 64 Mb reference, streamed in chunks of
+    args.stream_frags fragments (2 mates each, 16 windows per mate) through the
+    filtered path with double-buffered host<->device copies; timed end to end."""
+    import torch
+
+    import paper_1304_0681_amd as sw
+    import synth
+    from paper_1304_0681_amd import train as tr
+    from paper_1304_0681_amd.stream import HostChunk, StreamAligner
+
+    t0 = time.perf_counter()
+    t_map = 2 * 150
+    ref = synth.make_reference(synth.rng(synth.BASE_SEED + 5), 64_000_000)
+    # the filter: trained and calibrated on mates of its own (labels from plain SW)
+    b_tr = synth.paired_chunk(synth.BASE_SEED + 510, 100_000, ref)
+    db_tr = sw.DeviceBatch.from_synth(ctx, b_tr)
+    p_tr = tr.plain_scores(ctx, db_tr)
+    feat, y = tr.features_and_labels(ctx, db_tr, p_tr)
+    mlp, _ = tr.train(ctx, feat, y, steps=args.train_steps, batch=4096, seed=1)
+    del feat, y, p_tr, db_tr, b_tr
+    b_ca = synth.paired_chunk(synth.BASE_SEED + 511, 100_000, ref)
+    db_ca = sw.DeviceBatch.from_synth(ctx, b_ca)
+    p_ca = tr.plain_scores(ctx, db_ca)
+    f_ca, _ = tr.features_and_labels(ctx, db_ca, p_ca)
+    z = tr.logits_of(ctx, mlp, f_ca).cpu().numpy()
+    drop, lo, hi, _ = tr.calibrate_output(z, p_ca.hits[:, 0].cpu().numpy(),
+                                          p_ca.best_score.cpu().numpy(),
+                                          b_ca.windows["read_id"].astype(np.int64), t_map,
+                                          target=0.9995)
+    del f_ca, p_ca, db_ca, b_ca
+    # two distinct chunks, generated once and cycled (the generator is far slower
+    # than the GPU); plain SW on each gives the recall reference
+    chunks = [synth.paired_chunk(synth.BASE_SEED + 500 + k, args.stream_frags, ref)
+              for k in range(2)]
+    plain_best, plain_ms = [], []
+    for b in chunks:
+        db = sw.DeviceBatch.from_synth(ctx, b)
+        hits = torch.empty((b.n_pairs, 3), dtype=torch.int32, device="cuda")
+        bp = torch.empty(b.n_reads, dtype=torch.int32, device="cuda")
+        bs = torch.empty(b.n_reads, dtype=torch.int32, device="cuda")
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            db.pack_reads()
+            sw.sw_batch_score(ctx, db, SCORING, 0, hits)
+            sw.sw_best_per_read(ctx, db, hits, t_map, bp, bs)
+            torch.cuda.synchronize()
+        plain_ms.append((time.perf_counter() - t) * 1e3)
+        plain_best.append(bs.cpu().numpy())
+        del db, hits, bp, bs
+    hcs = [HostChunk(b) for b in chunks]
+    rc = max(h.n_reads for h in hcs)
+    st = StreamAligner(ctx, chunks[0].ref, mlp, (drop, lo, hi), t_map, reads_cap=rc,
+                       bases_cap=max(h.n_bases for h in hcs), pairs_cap=max(h.n_pairs for h in hcs),
+                       ops_stride=64)
+    stats = {"miss": 0, "mapped": 0, "kept": 0, "trunc": 0, "mates": 0}
+
+    def consume(i, r):
+        best = plain_best[i % 2]
+        m = best >= t_map
+        stats["mapped"] += int(m.sum())
+        stats["miss"] += int((r["best_score"][m] != best[m]).sum())
+        stats["kept"] += r["kept"]
+        stats["trunc"] += int(np.count_nonzero(r["aln"]["status"] & 1))
+        stats["mates"] += len(best)
+
+    st.run([hcs[0], hcs[1]])                      # warm-up
+    n_chunks = args.stream_chunks
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st.run([hcs[k % 2] for k in range(n_chunks)], consume)
+    wall = time.perf_counter() - t1
+    mates = stats["mates"]
+    pairs = sum(hcs[k % 2].n_pairs for k in range(n_chunks))
+    sw.sw_mlp_destroy(ctx, mlp)
+    return {
+        "workload": f"paired reads: {n_chunks} chunks of {args.stream_frags} fragments "
+                    f"(insert 200-500 nt, 2 x 150-nt mates) from a 64 Mb reference, 16 windows of "
+                    f"200-1000 nt per mate; 2 distinct chunks generated and cycled",
+        "chunks": n_chunks, "mates": mates, "fragments": mates // 2, "pairs": pairs,
+        "wall_seconds": round(wall, 3),
+        "mates_per_s": round(mates / wall, 1),
+        "fragments_per_s": round(mates / 2 / wall, 1),
+        "ms_per_chunk": round(wall / n_chunks * 1e3, 3),
+        "plain_sw_ms_per_chunk_device_resident": round(float(np.mean(plain_ms)), 3),
+        "kept_pairs_fraction": round(stats["kept"] / pairs, 5),
+        "best_hit_recall_mapped_mates": round(1 - stats["miss"] / max(stats["mapped"], 1), 6),
+        "mapped_fraction": round(stats["mapped"] / mates, 5),
+        "cigar_truncated": stats["trunc"],
+        "t_map": t_map, "thresholds": [drop, lo, hi],
+        "includes": "host->device copies of reads and windows, encode, features, MLP, decision, "
+                    "compaction, SW on kept pairs, best hit, traceback, device->host copies",
+        "setup_seconds": round(time.perf_counter() - t0 - wall, 1),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,6 +406,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--no-spliced", action="store_true", help="skip the spliced-seed traceback pass")
     ap.add_argument("--spliced-reads", type=int, default=200_000)
+    ap.add_argument("--no-stream", action="store_true", help="skip the paired-read stream")
+    ap.add_argument("--stream-frags", type=int, default=500_000,
+                    help="fragments per chunk (2 mates each)")
+    ap.add_argument("--stream-chunks", type=int, default=20)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -429,6 +530,9 @@ def main():
     if not args.no_spliced:
         log("spliced seeds ...")
         out["spliced"] = bench_spliced(ctx, args)
+    if not args.no_stream:
+        log("paired-read stream ...")
+        out["stream"] = bench_stream(ctx, args)
     sw.sw_ctx_destroy(ctx)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

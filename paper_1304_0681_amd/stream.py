@@ -1,0 +1,198 @@
+"""Streaming of read chunks through the filtered alignment path on one GPU.
+
+The paper's pipeline moves reads through its stages in batches, with stages
+overlapping each other (Sec. 3, the batch queues between stages).  Here a chunk
+of reads (with all of their candidate windows) is one batch.  Each chunk is:
+
+  host -> device copy of the reads, read offsets/lengths and windows
+  encode (sw_pack2b), learned filter (sw_filter_candidates: features, MLP,
+  per-read decision, compaction), SW on the kept pairs (sw_batch_score), best
+  hit per read (sw_best_per_read with the mapping threshold), traceback of the
+  best hit (sw_batch_traceback)
+  device -> host copy of the per-read results
+
+Two device buffer sets and three streams (host-to-device copies, compute,
+device-to-host copies) overlap the copies of chunks i + 1 and i - 1 with the
+compute of chunk i.  The reference stays resident (packed once); host buffers
+are pinned allocations so that the copies are asynchronous.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import (ALN_DTYPE, WINDOW_DTYPE, _ptr, sw_batch, sw_batch_score, sw_batch_traceback,
+               sw_best_per_read, sw_filter_candidates, sw_pack2b)
+
+SCORING = (5, -4, -10, -1)
+
+
+class _View:
+    """A batch over device buffers (the object the binding functions take)."""
+
+    def __init__(self, c, n_reads, n_pairs):
+        self.c, self.n_reads, self.n_pairs = c, n_reads, n_pairs
+
+
+class HostChunk:
+    """One chunk's inputs in pinned host memory."""
+
+    def __init__(self, b):
+        import torch
+        self.n_reads, self.n_pairs, self.n_bases = b.n_reads, b.n_pairs, len(b.reads)
+        self.reads = torch.empty(self.n_bases, dtype=torch.uint8, pin_memory=True)
+        self.reads.numpy()[:] = b.reads
+        self.read_off = torch.empty(self.n_reads, dtype=torch.int64, pin_memory=True)
+        self.read_off.numpy()[:] = b.read_off.view(np.int64)
+        self.read_len = torch.empty(self.n_reads, dtype=torch.int16, pin_memory=True)
+        self.read_len.numpy()[:] = b.read_len.view(np.int16)
+        self.win = torch.empty(self.n_pairs * WINDOW_DTYPE.itemsize, dtype=torch.uint8,
+                               pin_memory=True)
+        self.win.numpy()[:] = np.ascontiguousarray(b.windows).view(np.uint8)
+
+
+class _DeviceSet:
+    def __init__(self, reads_cap, bases_cap, pairs_cap, ops_stride):
+        import torch
+        d = "cuda"
+        self.reads = torch.empty(bases_cap, dtype=torch.uint8, device=d)
+        self.reads2b = torch.empty((bases_cap + 15) // 16, dtype=torch.int32, device=d)
+        self.read_off = torch.empty(reads_cap, dtype=torch.int64, device=d)
+        self.read_len = torch.empty(reads_cap, dtype=torch.int16, device=d)
+        self.win = torch.empty(pairs_cap * WINDOW_DTYPE.itemsize, dtype=torch.uint8, device=d)
+        self.bad = torch.zeros(1, dtype=torch.int32, device=d)
+        self.feat = torch.empty((pairs_cap, 64), dtype=torch.int16, device=d)
+        self.logits = torch.empty(pairs_cap, dtype=torch.float32, device=d)
+        self.keep = torch.empty(pairs_cap, dtype=torch.uint8, device=d)
+        self.win_out = torch.empty(pairs_cap * WINDOW_DTYPE.itemsize, dtype=torch.uint8, device=d)
+        self.sel = torch.empty(pairs_cap, dtype=torch.int32, device=d)
+        self.n_sel = torch.zeros(1, dtype=torch.int32, device=d)
+        self.n_unsure = torch.zeros(1, dtype=torch.int32, device=d)
+        self.hits = torch.empty((pairs_cap, 3), dtype=torch.int32, device=d)
+        self.best_pair = torch.empty(reads_cap, dtype=torch.int32, device=d)
+        self.best_score = torch.empty(reads_cap, dtype=torch.int32, device=d)
+        self.mapped = torch.empty(reads_cap, dtype=torch.uint8, device=d)
+        self.aln = torch.empty((reads_cap, 7), dtype=torch.int32, device=d)
+        self.ops = torch.empty((reads_cap, ops_stride), dtype=torch.int32, device=d)
+        self.pair = torch.empty(reads_cap, dtype=torch.int32, device=d)
+        self.h2d = torch.cuda.Event()
+        self.done = torch.cuda.Event()
+        self.free = None           # event after which the set may be overwritten
+
+
+class _HostOut:
+    def __init__(self, reads_cap, ops_stride):
+        import torch
+        self.best_score = torch.empty(reads_cap, dtype=torch.int32, pin_memory=True)
+        self.mapped = torch.empty(reads_cap, dtype=torch.uint8, pin_memory=True)
+        self.pair = torch.empty(reads_cap, dtype=torch.int32, pin_memory=True)
+        self.aln = torch.empty((reads_cap, 7), dtype=torch.int32, pin_memory=True)
+        self.ops = torch.empty((reads_cap, ops_stride), dtype=torch.int32, pin_memory=True)
+        self.n_sel = torch.empty(1, dtype=torch.int32, pin_memory=True)
+        self.d2h = torch.cuda.Event()
+        self.pending = None        # (chunk index, n_reads) waiting to be handed out
+
+
+class StreamAligner:
+    """Filtered alignment of a stream of chunks against one resident reference.
+
+    `thresholds` = (drop, lo, hi) of the filter's decision rule; `t_map` is the
+    mapping threshold of sw_best_per_read.  run() hands every chunk's results to
+    `consume(index, results)` as numpy arrays: best_score, mapped, pair (index of
+    the best window in the chunk's window list, -1 if none), aln, ops, kept
+    (pairs aligned)."""
+
+    def __init__(self, ctx, ref_ascii: np.ndarray, mlp, thresholds, t_map: int, reads_cap: int,
+                 bases_cap: int, pairs_cap: int, ops_stride: int = 64, scoring=SCORING):
+        import torch
+        self.ctx, self.mlp, self.scoring, self.t_map = ctx, mlp, scoring, int(t_map)
+        self.drop, self.lo, self.hi = (float(x) for x in thresholds)
+        self.ops_stride = int(ops_stride)
+        self.caps = (reads_cap, bases_cap, pairs_cap)
+        d = "cuda"
+        self.ref_ascii = torch.from_numpy(np.ascontiguousarray(ref_ascii)).to(d)
+        self.ref_len = len(ref_ascii)
+        self.ref2b = torch.empty((self.ref_len + 15) // 16, dtype=torch.int32, device=d)
+        bad = torch.zeros(1, dtype=torch.int32, device=d)
+        sw_pack2b(ctx, self.ref_ascii, self.ref_len, self.ref2b, bad)
+        torch.cuda.synchronize()
+        del self.ref_ascii
+        self.sets = [_DeviceSet(reads_cap, bases_cap, pairs_cap, ops_stride) for _ in range(2)]
+        self.outs = [_HostOut(reads_cap, ops_stride) for _ in range(2)]
+        self.s_h2d, self.s_comp, self.s_d2h = (torch.cuda.Stream() for _ in range(3))
+
+    def _batch(self, ds, hc, win, n_pairs_dev=None):
+        c = sw_batch(_ptr(self.ref2b), self.ref_len, _ptr(ds.reads2b), hc.n_bases, _ptr(ds.read_off),
+                     _ptr(ds.read_len), hc.n_reads, _ptr(win), hc.n_pairs, _ptr(n_pairs_dev))
+        return _View(c, hc.n_reads, hc.n_pairs)
+
+    def _compute(self, ds, hc):
+        s = self.s_comp
+        full = self._batch(ds, hc, ds.win)
+        sw_pack2b(self.ctx, ds.reads, hc.n_bases, ds.reads2b, ds.bad, s)
+        ds.n_unsure.zero_()
+        sw_filter_candidates(self.ctx, full, self.mlp, self.lo, self.hi, ds.feat, ds.logits, ds.keep,
+                             ds.win_out, ds.sel, ds.n_sel, ds.n_unsure, s, logit_drop=self.drop)
+        kept = self._batch(ds, hc, ds.win_out, ds.n_sel)
+        sw_batch_score(self.ctx, kept, self.scoring, 0, ds.hits, s)
+        sw_best_per_read(self.ctx, kept, ds.hits, self.t_map, ds.best_pair, ds.best_score,
+                         ds.mapped, s)
+        sw_batch_traceback(self.ctx, kept, self.scoring, ds.best_pair, hc.n_reads, ds.aln, ds.ops,
+                           self.ops_stride, s)
+        # index of the best window in the chunk's own window list (data movement only)
+        n = hc.n_reads
+        bp = ds.best_pair[:n].long()
+        ds.pair[:n] = ds.sel[bp.clamp(min=0)].where(bp >= 0, bp.new_full((), -1)).int()
+
+    def _hand_out(self, ho, consume):
+        idx, n = ho.pending
+        ho.d2h.synchronize()
+        consume(idx, dict(best_score=ho.best_score[:n].numpy().copy(),
+                          mapped=ho.mapped[:n].numpy().astype(bool),
+                          pair=ho.pair[:n].numpy().copy(),
+                          aln=ho.aln[:n].numpy().copy().view(ALN_DTYPE).reshape(-1),
+                          ops=ho.ops[:n].numpy().copy().view(np.uint32),
+                          kept=int(ho.n_sel[0])))
+        ho.pending = None
+
+    def run(self, chunks, consume=None):
+        """Process the HostChunk sequence `chunks` in order."""
+        import torch
+        consume = consume or (lambda i, r: None)
+        rc, bc, pc = self.caps
+        for i, hc in enumerate(chunks):
+            if hc.n_reads > rc or hc.n_bases > bc or hc.n_pairs > pc:
+                raise ValueError("chunk exceeds the stream's capacity")
+            ds, ho = self.sets[i % 2], self.outs[i % 2]
+            # host -> device, once the set's previous chunk has been copied out
+            if ds.free is not None:
+                self.s_h2d.wait_event(ds.free)
+            with torch.cuda.stream(self.s_h2d):
+                ds.reads[:hc.n_bases].copy_(hc.reads, non_blocking=True)
+                ds.read_off[:hc.n_reads].copy_(hc.read_off, non_blocking=True)
+                ds.read_len[:hc.n_reads].copy_(hc.read_len, non_blocking=True)
+                ds.win[:hc.win.numel()].copy_(hc.win, non_blocking=True)
+                ds.h2d.record(self.s_h2d)
+            self.s_comp.wait_event(ds.h2d)
+            with torch.cuda.stream(self.s_comp):
+                self._compute(ds, hc)
+                ds.done.record(self.s_comp)
+            # the pinned output set still holds chunk i - 2: hand it out first
+            if ho.pending is not None:
+                self._hand_out(ho, consume)
+            self.s_d2h.wait_event(ds.done)
+            n = hc.n_reads
+            with torch.cuda.stream(self.s_d2h):
+                ho.best_score[:n].copy_(ds.best_score[:n], non_blocking=True)
+                ho.mapped[:n].copy_(ds.mapped[:n], non_blocking=True)
+                ho.pair[:n].copy_(ds.pair[:n], non_blocking=True)
+                ho.aln[:n].copy_(ds.aln[:n], non_blocking=True)
+                ho.ops[:n].copy_(ds.ops[:n], non_blocking=True)
+                ho.n_sel.copy_(ds.n_sel, non_blocking=True)
+                ho.d2h.record(self.s_d2h)
+            ho.pending = (i, n)
+            ds.free = ho.d2h
+        for k in range(len(chunks), len(chunks) + 2):
+            ho = self.outs[k % 2]
+            if ho.pending is not None:
+                self._hand_out(ho, consume)
+        torch.cuda.synchronize()
