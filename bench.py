@@ -55,6 +55,13 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9
 PEAK_GCUPS_INT32 = VALU_LANE_OPS / 10 / 1e9
 PEAK_GCUPS_INT16X2 = VALU_LANE_OPS / 5.5 / 1e9
 PATHS = {1: "int32", 2: "int32+ends", 3: "int16x2"}
+# HBM bytes per launch of the dominant kernel on the default workload, from two
+# rocprofv3 PMC runs (FETCH_SIZE, then WRITE_SIZE) of this script with
+# --copy-probe, each scaled by what the counter reads for a 1 GiB device copy
+# (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000); recorded with the counters in
+# profiles/k_sw_score16_config2_plain.md.  Valid only while that kernel and the
+# workload stay as they were measured.
+MEASURED_TRAFFIC = {("k_sw_score16", 4, 25, 1_000_000): 1.841e9}
 
 
 def log(*a):
@@ -473,6 +480,7 @@ def main():
     gcups = cells / (ms_step / 1e3) / 1e9
     reads_s = b.n_reads / (ms_step / 1e3)
     dom = int(np.argmax(class_ms))
+    tune_shape = next(((t["G"], t["RPL"]) for t in (tune or []) if t["m_max"] == 100), (4, 25))
     dom_ms = class_ms[dom] / args.steps
     path = PATHS.get(paths[dom], "int32")
     peak = PEAK_GCUPS_INT16X2 if path == "int16x2" else PEAK_GCUPS_INT32
@@ -514,7 +522,9 @@ def main():
             "peak": round(peak, 1),
             "unit": "GCUPS",
             "frac": round(kern_gcups / peak, 4),
-            "traffic": None,
+            "traffic": MEASURED_TRAFFIC.get(
+                ("k_sw_score16" if path == "int16x2" else "k_sw_score", tune_shape[0], tune_shape[1],
+                 b.n_reads)),
             "kernel_ms": round(float(np.mean(score_ms)), 3),
             "frac_of_int32_roofline": round(kern_gcups / PEAK_GCUPS_INT32, 4),
         },
