@@ -243,9 +243,14 @@ sw_status sw_mlp_train_step(sw_ctx *ctx, sw_mlp *mlp, const uint16_t *d_x, const
                             uint32_t n, float lr, float *d_loss, void *stream);
 
 /* Training labels from plain scores: d_y[p] = 1 if score(p) >= best score of
- * its read - margin (d_best_score from sw_best_per_read), else 0. */
+ * its read - margin and that best score is >= min_best (d_best_score from
+ * sw_best_per_read), else 0.  min_best = INT32_MIN gives the plain margin label;
+ * min_best = the mapping threshold labels only candidates that can become the
+ * record of a mapped read (stage E task iv), which is what a rule that may skip
+ * predicted-unmapped reads needs. */
 sw_status sw_mlp_labels(sw_ctx *ctx, const sw_batch *batch, const sw_hit *d_hits,
-                        const int32_t *d_best_score, int32_t margin, float *d_y, void *stream);
+                        const int32_t *d_best_score, int32_t margin, int32_t min_best, float *d_y,
+                        void *stream);
 
 /* Filter step: features (into d_feat[n_pairs * 64]), logits (d_logits[n_pairs]),
  * per-read decision (d_keep[n_pairs]: a read whose best logit is below

@@ -99,7 +99,7 @@ def lib() -> ctypes.CDLL:
         L.sw_mlp_forward.argtypes = [P, P, P, U32, P, P]
         L.sw_mlp_grad.argtypes = [P, P, P, P, U32, P, P, P]
         L.sw_mlp_train_step.argtypes = [P, P, P, P, U32, F, P, P]
-        L.sw_mlp_labels.argtypes = [P, ctypes.POINTER(sw_batch), P, P, I32, P, P]
+        L.sw_mlp_labels.argtypes = [P, ctypes.POINTER(sw_batch), P, P, I32, I32, P, P]
         L.sw_filter_candidates.argtypes = [P, ctypes.POINTER(sw_batch), P,
                                            ctypes.POINTER(sw_filter_params), P, P, P, P, P, P, P, P]
         L.sw_autotune.argtypes = [P, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scoring), U32,
@@ -228,9 +228,10 @@ def sw_mlp_train_step(ctx, mlp, d_x, d_y, n, lr, d_loss=None, stream=None):
                                         _ptr(d_loss), _stream_ptr(stream)))
 
 
-def sw_mlp_labels(ctx, batch, d_hits, d_best_score, margin, d_y, stream=None):
+def sw_mlp_labels(ctx, batch, d_hits, d_best_score, margin, d_y, stream=None,
+                  min_best=-(1 << 31)):
     _check(ctx, lib().sw_mlp_labels(ctx, ctypes.byref(batch.c), _ptr(d_hits), _ptr(d_best_score),
-                                    int(margin), _ptr(d_y), _stream_ptr(stream)))
+                                    int(margin), int(min_best), _ptr(d_y), _stream_ptr(stream)))
 
 
 def sw_filter_candidates(ctx, batch, mlp, logit_lo, logit_hi, d_feat, d_logits, d_keep,

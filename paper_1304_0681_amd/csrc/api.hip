@@ -871,7 +871,8 @@ sw_status sw_mlp_train_step(sw_ctx *ctx, sw_mlp *mlp, const uint16_t *d_x, const
 }
 
 sw_status sw_mlp_labels(sw_ctx *ctx, const sw_batch *b, const sw_hit *d_hits,
-                        const int32_t *d_best_score, int32_t margin, float *d_y, void *stream)
+                        const int32_t *d_best_score, int32_t margin, int32_t min_best, float *d_y,
+                        void *stream)
 {
     if (!ctx)
         return fail(nullptr, SW_E_INVALID, "ctx is NULL");
@@ -883,7 +884,7 @@ sw_status sw_mlp_labels(sw_ctx *ctx, const sw_batch *b, const sw_hit *d_hits,
     if (!d_hits || !d_best_score || !d_y)
         return fail(ctx, SW_E_INVALID, "NULL buffer");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    HIP_TRY(ctx, mlp_labels(b->n_pairs, b->d_win, d_hits, d_best_score, margin, d_y,
+    HIP_TRY(ctx, mlp_labels(b->n_pairs, b->d_win, d_hits, d_best_score, margin, min_best, d_y,
                             static_cast<hipStream_t>(stream)));
     return SW_OK;
 }

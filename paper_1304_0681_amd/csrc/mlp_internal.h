@@ -36,7 +36,7 @@ size_t mlp_workspace_bytes(uint32_t B);
 hipError_t mlp_adam(float *theta, float *m, float *v, const float *g, float lr, int step,
                     hipStream_t st);
 hipError_t mlp_labels(uint32_t n_pairs, const sw_window *win, const sw_hit *hits,
-                      const int32_t *best, int32_t margin, float *y, hipStream_t st);
+                      const int32_t *best, int32_t margin, int32_t min_best, float *y, hipStream_t st);
 hipError_t read_segments(uint32_t n_pairs, const uint32_t *d_n, const sw_window *win,
                          uint32_t n_reads, uint32_t *first, uint32_t *last, uint32_t *count,
                          hipStream_t st);

@@ -52,12 +52,16 @@ def plain_scores(ctx, db: DeviceBatch, scoring=SCORING):
     return PlainResult(hits, bp, bs)
 
 
-def features_and_labels(ctx, db: DeviceBatch, plain: PlainResult, margin: int = 10):
+def features_and_labels(ctx, db: DeviceBatch, plain: PlainResult, margin: int = 10,
+                        min_best: int | None = None):
+    """Features of every pair and labels: within `margin` of the read's best plain
+    score (and, with min_best, only for reads whose best score reaches it)."""
     import torch
     feat = torch.empty((db.n_pairs, 64), dtype=torch.int16, device="cuda")
     y = torch.empty(db.n_pairs, dtype=torch.float32, device="cuda")
     sw_features(ctx, db, feat)
-    sw_mlp_labels(ctx, db, plain.hits, plain.best_score, margin, y)
+    sw_mlp_labels(ctx, db, plain.hits, plain.best_score, margin, y,
+                  min_best=-(1 << 31) if min_best is None else min_best)
     return feat, y
 
 

@@ -272,6 +272,66 @@ def config4(seed: int = BASE_SEED + 4, n_reads: int = 1_000_000, **kw) -> Batch:
     return config2(seed=seed, n_reads=n_reads, k_fixed=16, **kw)
 
 
+def seeded_decoys(g, ref: np.ndarray, codes: np.ndarray, win: np.ndarray, truth: dict,
+                  k: int = 15, chunk: int = 1 << 20) -> None:
+    """Move decoy windows (in place) to where one of their read's k-mers occurs.
+
+    For each decoy a k-mer of the query (the read, or its reverse complement for
+    a strand-1 window) is drawn at a uniform position p; if it occurs in the
+    reference away from the read's origin, the window is placed around the
+    alignment that occurrence implies (query start = occurrence - p), as true
+    windows are placed around the origin.  Decoys whose k-mer does not occur
+    elsewhere stay where they were."""
+    L = len(ref)
+    m = codes.shape[1]
+    n = L - k + 1
+    v = np.zeros(n, dtype=np.int64)
+    for t in range(k):
+        v |= ref[t:t + n].astype(np.int64) << (2 * t)
+    order = np.argsort(v, kind="stable")
+    sv = v[order]
+    dec_all = np.nonzero((win["flags"] & FLAG_TRUE_ORIGIN) == 0)[0]
+    for a in range(0, len(dec_all), chunk):
+        dec = dec_all[a:a + chunk]
+        rid = win["read_id"][dec].astype(np.int64)
+        strand = win["strand"][dec].astype(bool)
+        p = g.integers(0, m - k + 1, size=len(dec))
+        # query base t of the k-mer: read[p + t], or 3 - read[m - 1 - (p + t)] on strand 1
+        t = np.arange(k)
+        fwd = codes[rid[:, None], p[:, None] + t[None, :]]
+        rev = 3 - codes[rid[:, None], (m - 1 - p)[:, None] - t[None, :]]
+        kq = np.where(strand[:, None], rev, fwd).astype(np.int64)
+        val = (kq << (2 * t[None, :])).sum(axis=1)
+        lo = np.searchsorted(sv, val, "left")
+        hi = np.searchsorted(sv, val, "right")
+        pick = lo + (g.random(len(dec)) * np.maximum(hi - lo, 1)).astype(np.int64)
+        pos = order[np.minimum(pick, n - 1)]
+        o = pos - p
+        w = win["len"][dec].astype(np.int64)
+        ok = (hi > lo) & (np.abs(o - truth["origin"][rid]) >= m) & (o >= 0) & (o + m <= L)
+        lo_s = np.maximum(0, o + m - w)
+        hi_s = np.minimum(o, L - w)
+        hi_s = np.maximum(hi_s, lo_s)
+        start = lo_s + (g.random(len(dec)) * (hi_s - lo_s + 1)).astype(np.int64)
+        win["ref_begin"][dec[ok]] = start[ok].astype(np.uint32)
+
+
+def config4_hard(seed: int = BASE_SEED + 40, n_reads: int = 1_000_000,
+                 repeat_frac: float = 0.2, ref_len: int = 4_000_000) -> Batch:
+    """Hard variant of the learned-filter workload: the config-4 reads and
+    windows on a reference of which `repeat_frac` is made of repeat families
+    (copies at 2-10 % divergence), with decoy windows placed where one of the
+    read's 15-mers occurs (uniform where none does)."""
+    g = rng(seed)
+    ref = make_reference(g, ref_len, gc=0.40)
+    plant_repeats(g, ref, repeat_frac)
+    codes, truth = sample_reads(g, ref, n_reads, 100, 0.01, 0.001, random_frac=0.05)
+    k = np.full(n_reads, 16, dtype=np.int64)
+    win = candidate_windows(g, len(ref), truth, k, 200, 600, 0.8)
+    seeded_decoys(g, ref, codes, win, truth, 15)
+    return _assemble_fixed(ref, codes, win, truth)
+
+
 def spliced(seed: int = BASE_SEED + 3, n_reads: int = 200_000, ref_len: int = 16_000_000,
             seed_len: int = 100, p_sub: float = 0.01, p_indel: float = 0.001) -> Batch:
     """Spliced long reads split into seeds.
