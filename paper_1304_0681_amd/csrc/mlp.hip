@@ -267,35 +267,40 @@ __global__ void __launch_bounds__(256) k_relu_back(const float *DA, const float 
 }
 
 // Column sums of a transposed bf16 matrix DT [cols][ldt] over its first `rows`
-// entries (bias gradients), and dw3/db3 from a2^T dz; fixed order.
+// entries, times w[r] when w is given (bias gradients; dw3 = a2^T dz).  One wave
+// per column: lane l adds rows l, l + 64, ... in order, then an xor butterfly
+// combines the lanes.  The order of every addition depends only on `rows`, so
+// the result is reproducible bit for bit.
 __global__ void __launch_bounds__(256) k_colsum_t(const uint16_t *DT, uint32_t ldt, uint32_t rows,
-                                                  uint32_t cols, float *out)
+                                                  uint32_t cols, const float *w, float *out)
 {
-    const uint32_t c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= cols)
+    const uint32_t c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63;
+    if (c >= cols)      // wave-uniform
         return;
+    const uint16_t *col = DT + (uint64_t)c * ldt;
     float s = 0.f;
-    for (uint32_t r = 0; r < rows; ++r)
-        s += bf2f(DT[(uint64_t)c * ldt + r]);
-    out[c] = s;
+    for (uint32_t r = lane; r < rows; r += 64)
+        s += bf2f(col[r]) * (w ? w[r] : 1.f);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        s += __shfl_xor(s, off);
+    if (lane == 0)
+        out[c] = s;
 }
 
-__global__ void __launch_bounds__(256) k_dw3(const uint16_t *A2T, uint32_t ldt, const float *dz,
-                                             uint32_t B, float *dw3, float *db3)
+// out[0] = (sum of x[0..n)) / div, one wave, in the same fixed order
+__global__ void __launch_bounds__(64) k_sum_div(const float *x, uint32_t n, float div, float *out)
 {
-    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j > kHidden)
-        return;
+    const uint32_t lane = threadIdx.x & 63;
     float s = 0.f;
-    if (j == kHidden) {
-        for (uint32_t b = 0; b < B; ++b)
-            s += dz[b];
-        db3[0] = s;
-        return;
-    }
-    for (uint32_t b = 0; b < B; ++b)
-        s += bf2f(A2T[(uint64_t)j * ldt + b]) * dz[b];
-    dw3[j] = s;
+    for (uint32_t r = lane; r < n; r += 64)
+        s += x[r];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        s += __shfl_xor(s, off);
+    if (lane == 0)
+        out[0] = s / div;
 }
 
 // X (bf16 [B x 64]) -> XT [64 x ldt]
@@ -319,16 +324,6 @@ __global__ void __launch_bounds__(256) k_scatter_grad(const float *G, uint32_t l
         return;
     const uint32_t i = idx / kHidden, o = idx % kHidden;
     g[idx] = G[(uint64_t)o * ld + i];
-}
-
-__global__ void __launch_bounds__(256) k_loss_sum(const float *terms, uint32_t B, float *loss)
-{
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        float s = 0.f;
-        for (uint32_t b = 0; b < B; ++b)
-            s += terms[b];
-        loss[0] = s / (float)B;
-    }
 }
 
 __global__ void __launch_bounds__(256) k_adam(float *theta, float *m, float *v, const float *g,
@@ -649,17 +644,21 @@ hipError_t mlp_backprop(const MlpDev &W, const uint16_t *X, const float *y, uint
     if ((e = mlp_gemm(A1, kHidden, W.w2t, kHidden, Z2, kHidden, B, kHidden, kHidden, st))) return e;
     hipLaunchKernelGGL(k_bias_relu, dim3(blocks_for(bh)), dim3(256), 0, st, Z2, W.b2, B, kHidden, A2, A2T, ldt);
     hipLaunchKernelGGL(k_head, dim3(blocks_for(B)), dim3(256), 0, st, W, A2, Z2, y, B, z, dz, DZ2, DZ2T, ldt, terms);
-    hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(256), 0, st, terms, B, loss);
+    hipLaunchKernelGGL(k_sum_div, dim3(1), dim3(64), 0, st, terms, B, (float)B, loss);
     // backward
-    hipLaunchKernelGGL(k_dw3, dim3(1), dim3(256), 0, st, A2T, ldt, dz, B, grad + kOffW3, grad + kOffB3);
-    hipLaunchKernelGGL(k_colsum_t, dim3(1), dim3(256), 0, st, DZ2T, ldt, B, kHidden, grad + kOffB2);
+    hipLaunchKernelGGL(k_colsum_t, dim3(kHidden / 4), dim3(256), 0, st, A2T, ldt, B, kHidden, dz,
+                       grad + kOffW3);
+    hipLaunchKernelGGL(k_sum_div, dim3(1), dim3(64), 0, st, dz, B, 1.f, grad + kOffB3);
+    hipLaunchKernelGGL(k_colsum_t, dim3(kHidden / 4), dim3(256), 0, st, DZ2T, ldt, B, kHidden,
+                       (const float *)nullptr, grad + kOffB2);
     // dW2^T[o][i] = sum_b dz2[b][o] a1[b][i]
     if ((e = mlp_gemm(DZ2T, ldt, A1T, ldt, GW, kHidden, kHidden, kHidden, ldt, st))) return e;
     hipLaunchKernelGGL(k_scatter_grad, dim3(blocks_for(kHidden * kHidden)), dim3(256), 0, st, GW, kHidden, kHidden, grad + kOffW2);
     // da1[b][i] = sum_o dz2[b][o] W2[i][o]
     if ((e = mlp_gemm(DZ2, kHidden, W.w2, kHidden, DA1, kHidden, B, kHidden, kHidden, st))) return e;
     hipLaunchKernelGGL(k_relu_back, dim3(blocks_for(bh)), dim3(256), 0, st, DA1, Z1, B, kHidden, DZ1T, ldt);
-    hipLaunchKernelGGL(k_colsum_t, dim3(1), dim3(256), 0, st, DZ1T, ldt, B, kHidden, grad + kOffB1);
+    hipLaunchKernelGGL(k_colsum_t, dim3(kHidden / 4), dim3(256), 0, st, DZ1T, ldt, B, kHidden,
+                       (const float *)nullptr, grad + kOffB1);
     // dW1^T[o][i] = sum_b dz1[b][o] x[b][i]
     if ((e = mlp_gemm(DZ1T, ldt, XT, ldt, GW, kIn, kHidden, kIn, ldt, st))) return e;
     hipLaunchKernelGGL(k_scatter_grad, dim3(blocks_for(kIn * kHidden)), dim3(256), 0, st, GW, kIn, kIn, grad + kOffW1);
