@@ -277,7 +277,7 @@ sw_status sw_filter_candidates(sw_ctx *ctx, const sw_batch *batch, const sw_mlp 
  * SW_OPT_BLOCKS_PER_CU: workgroups (4 waves each) per compute unit of the
  *   persistent scoring kernels, 1..64 (default 2).
  * SW_OPT_TB_SCRATCH_MB: device scratch of sw_batch_traceback in MiB, 1..65536
- *   (default 1024).  Each query-length class runs as many pairs at once as
+ *   (default 2048).  Each query-length class runs as many pairs at once as
  *   their direction codes fit; a class whose single largest slot does not fit
  *   marks its pairs with status bit 2 (score -1) instead of aligning them. */
 #define SW_OPT_INT16 1

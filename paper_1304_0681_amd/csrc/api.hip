@@ -42,7 +42,7 @@ struct sw_ctx {
     // traceback code slots: a fixed budget, sized once
     uint32_t *tb = nullptr;
     size_t tb_bytes = 0;
-    size_t tb_budget = 1ull << 30;
+    size_t tb_budget = 2ull << 30;
     // inside sw_graph_begin / sw_graph_end: no allocation, no host synchronisation
     bool capturing = false;
     // filter scratch: read segments (first, last, count) and compaction offsets
@@ -383,7 +383,7 @@ sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *b, const sw_scoring *s
     ctx->tb = static_cast<uint32_t *>(buf);
     ctx->tb_bytes = have;
     const int wpb = traceback_waves_per_block();
-    const int grid = std::max(1, ctx->n_cu * 8 / wpb);
+    const int grid = std::max(1, ctx->n_cu * 16 / wpb);
     for (int c = 0; c < kNumClasses; ++c) {
         if (c > 0 && (uint64_t)kDefaultClasses[c - 1].m_max >= b->reads_len)
             continue;   // no read of this batch can fall in this class

@@ -73,8 +73,6 @@ bool score_shape_available(int G, int RPL);
 int score_waves_per_block();
 hipError_t launch_best(const sw_batch &b, const sw_hit *hits, uint64_t *keys, int32_t t_map,
                        uint32_t *best_pair, int32_t *best_score, uint8_t *mapped, hipStream_t st);
-int traceback_rows_cap(int cls);
-int traceback_pairs_per_wave(int cls);
 int traceback_waves_per_block();
 hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &sc,
                                   const uint32_t *sel, const uint32_t *ids, const uint32_t *seg,

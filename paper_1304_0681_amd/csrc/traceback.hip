@@ -1,15 +1,17 @@
 // Traceback: full alignments with CIGAR for selected pairs.
 //
 // The DP of the score kernel is recomputed with the same lane layout (G lanes
-// per pair, RPL rows per lane, RPL a multiple of 8).  Every cell stores a
+// per pair, RPL rows per lane).  Every cell stores a
 // 4-bit direction code in a per-pair slot of device scratch:
 //   bits 0-1  H source: 0 stop (H == 0), 1 diagonal, 2 deletion (E), 3 insertion
 //             (first true in that order)
 //   bit 2     the deletion value of the NEXT column extends rather than opens
 //             (E(i,c) + gap_extend > H(i,c) + gap_open)
 //   bit 3     the insertion value of the NEXT row extends rather than opens
-// Column c stores its rows contiguously (8 codes per 32-bit word), so each
-// lane writes RPL/8 whole words per step.  The first lane of each group then
+// Column c stores its rows lane by lane: a lane's RPL rows fill ceil(RPL/8)
+// 32-bit words (8 codes each), so each lane writes whole words per step and a
+// tile needs no multiple of 8 rows per lane (104 rows cover 100-nt queries,
+// 160 rows 150-nt ones).  The first lane of each group then
 // walks back from the end cell (smallest window column, then smallest read row
 // among the maxima) under the canonical rule and run-length encodes the ops.
 #include "internal.h"
@@ -88,10 +90,9 @@ __device__ __forceinline__ uint32_t tb_window_word(const TBParams &P, int64_t rb
 template <int G, int RPL, bool STRIP>
 __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
 {
-    static_assert(RPL % 8 == 0, "codes are stored 8 per word");
     constexpr int PPW = 64 / G;
     constexpr int SR = G * RPL;
-    constexpr int WPL = RPL / 8;   // code words per lane per column
+    constexpr int WPL = (RPL + 7) / 8;   // code words per lane per column
     const int lane = threadIdx.x & 63;
     const int grp = lane / G;
     const int l = lane % G;
@@ -106,8 +107,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
     // Waves whose slots do not fit the scratch take no work; with no room for
     // even one wave every pair of the class is marked and skipped.
     const uint64_t nmax = P.maxlen[P.cls], mmax = P.maxlen[kNumClasses + P.cls];
-    const uint64_t rows_max = STRIP ? (mmax + SR - 1) / SR * SR : (uint64_t)SR;
-    const uint64_t slot_words = rows_max / 8 * nmax + (STRIP ? 2 * nmax : 0) + mmax + nmax + 8;
+    const uint64_t strips_max = STRIP ? (mmax + SR - 1) / SR : 1;
+    const uint64_t slot_words = strips_max * G * WPL * nmax + (STRIP ? 2 * nmax : 0) + mmax + nmax + 8;
     const uint64_t fit = P.codes_words / ((uint64_t)PPW * slot_words);
     const bool no_room = fit == 0;
     if (!no_room && wave_global >= fit)
@@ -143,8 +144,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
         const int T = n_wave + G - 1;
         const int m_wave = STRIP ? tb_wave_max(m) : SR;
         const int n_strips = STRIP ? (m_wave + SR - 1) / SR : 1;
-        const int rows_cap = n_strips * SR;          // rows stored per column
-        const uint32_t col_words = (uint32_t)rows_cap / 8;
+        const uint32_t col_words = (uint32_t)(n_strips * G * WPL);   // code words per column
         const uint64_t code_words = (uint64_t)col_words * (uint64_t)n_wave;
         int2 *bnd = reinterpret_cast<int2 *>(slot_codes + code_words);  // strip boundary row
         uint32_t *runs = slot_codes + code_words + (STRIP ? 2 * (uint64_t)n_wave : 0);
@@ -172,14 +172,16 @@ __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
                     prof[r] = (int)0x80808080u;
                 }
             }
-            int H[RPL], E[RPL], bh[RPL], bj[RPL];
+            int H[RPL], E[RPL];
 #pragma unroll
             for (int r = 0; r < RPL; ++r) {
                 H[r] = 0;
                 E[r] = go;
-                bh[r] = 0;
-                bj[r] = 0x7FFFFFFF;
             }
+            // this lane's best cell of the strip: columns arrive in increasing order, so
+            // a strictly larger column maximum keeps the smallest column, and the smallest
+            // row holding that maximum in the column is taken
+            int lbest = 0, lcol = 0x7FFFFFFF, lrow = 0x7FFFFFFF;
             int hup_prev = 0, gout = 0;
             const bool read_bnd = STRIP && strip > 0;
             const bool write_bnd = STRIP && strip + 1 < n_strips;
@@ -211,6 +213,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
 #pragma unroll
                     for (int q = 0; q < WPL; ++q)
                         cw[q] = 0;
+                    int cmax = 0;
 #pragma unroll
                     for (int r = 0; r < RPL; ++r) {
                         const int s = __builtin_amdgcn_sbfe(prof[r], rc8, wd);
@@ -221,18 +224,29 @@ __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
                         const uint32_t src = h == 0 ? 0u : (h == dd ? 1u : (h == e ? 2u : 3u));
                         H[r] = h;
                         const int hg = h + go;
-                        const uint32_t eext = (e + ge > hg) ? 4u : 0u;
-                        const uint32_t fext = (g + ge > hg) ? 8u : 0u;
-                        E[r] = max(e + ge, hg);
-                        g = max(max(g + ge, hg), 0);
-                        cw[r >> 3] |= (src | eext | fext) << (4 * (r & 7));
-                        const bool better = valid && h > bh[r];
-                        bh[r] = better ? h : bh[r];
-                        bj[r] = better ? c : bj[r];
+                        const int en = max(e + ge, hg);
+                        const int gn = max(max(g + ge, hg), 0);
+                        // the next column's deletion / next row's insertion extends when its
+                        // new value is not the open value (an open wins ties); a clamped
+                        // insertion value (0) is never the source of a positive H
+                        const uint32_t ext = (en != hg ? 4u : 0u) | (gn != hg ? 8u : 0u);
+                        E[r] = en;
+                        g = gn;
+                        cw[r >> 3] |= (src | ext) << (4 * (r & 7));
+                        cmax = max(cmax, h);
                     }
                     gout = g;
+                    if (valid && cmax > lbest) {
+                        int row = RPL;
+#pragma unroll
+                        for (int r = RPL - 1; r >= 0; --r)
+                            row = H[r] == cmax ? r : row;
+                        lbest = cmax;
+                        lcol = c;
+                        lrow = row0 + row;
+                    }
                     if (valid) {
-                        uint32_t *dst = slot_codes + (uint64_t)c * col_words + (uint32_t)(row0 >> 3);
+                        uint32_t *dst = slot_codes + (uint64_t)c * col_words + (uint32_t)((strip * G + l) * WPL);
 #pragma unroll
                         for (int q = 0; q < WPL; ++q)
                             dst[q] = cw[q];
@@ -242,16 +256,14 @@ __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
                 }
                 cur = nxt;
             }
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-                const int row = row0 + r;
-                const bool better = bh[r] > best ||
-                                    (bh[r] == best && bh[r] > 0 &&
-                                     (bj[r] < cbest || (bj[r] == cbest && row < rbest)));
+            {
+                const bool better = lbest > best ||
+                                    (lbest == best && lbest > 0 &&
+                                     (lcol < cbest || (lcol == cbest && lrow < rbest)));
                 if (better) {
-                    best = bh[r];
-                    cbest = bj[r];
-                    rbest = row;
+                    best = lbest;
+                    cbest = lcol;
+                    rbest = lrow;
                 }
             }
         }
@@ -279,9 +291,37 @@ __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
                 // walk back; runs are collected last-to-first in `runs`
                 int i = rbest, c = cbest, state = 0, bi = rbest, bc = cbest;
                 uint32_t nruns = 0, cur_op = 0xFFu, cur_len = 0;
+                // Most steps of the walk follow a diagonal (match runs), so a miss
+                // loads the code words of the next 8 cells of the diagonal at once
+                // (independent loads; indices clamped into the slot, and a clamped
+                // entry is never asked for) and the following steps read registers.
+                uint32_t pw[8];
+                int pi = -(1 << 30), pc = -(1 << 30);      // the diagonal held starts at (pi, pc)
+                // word of row ii within a column, and the row's code position in it
+                auto row_word = [&](int ii) -> uint32_t {
+                    const int sp = ii / SR, rs = ii - sp * SR, ln = rs / RPL, r = rs - ln * RPL;
+                    return (uint32_t)((sp * G + ln) * WPL + (r >> 3));
+                };
+                auto row_shift = [&](int ii) -> uint32_t { return 4u * (uint32_t)(((ii % SR) % RPL) & 7); };
                 auto code_at = [&](int ii, int cc) -> uint32_t {
-                    const uint32_t wv = slot_codes[(uint64_t)cc * col_words + (uint32_t)(ii >> 3)];
-                    return (wv >> (4 * (ii & 7))) & 15u;
+                    const int k = pc - cc;
+                    uint32_t wv;
+                    if (k >= 0 && k < 8 && pi - ii == k) {
+                        wv = pw[0];
+#pragma unroll
+                        for (int q = 1; q < 8; ++q)
+                            wv = k == q ? pw[q] : wv;
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int c2 = max(cc - q, 0), i2 = max(ii - q, 0);
+                            pw[q] = slot_codes[(uint64_t)c2 * col_words + row_word(i2)];
+                        }
+                        pi = ii;
+                        pc = cc;
+                        wv = pw[0];
+                    }
+                    return (wv >> row_shift(ii)) & 15u;
                 };
                 const uint32_t max_runs = (uint32_t)(m + n + 2);
                 auto emit = [&](uint32_t op) {
@@ -365,13 +405,11 @@ hipError_t tb_launch(const TBParams &p, int grid, hipStream_t st)
 
 }  // namespace
 
-// Traceback shapes per query-length class (RPL a multiple of 8).
+// Traceback shapes per query-length class (G lanes x RPL rows >= the class bound).
 static const ClassShape kTBShapes[kNumClasses] = {
-    {16, 2, 8},   {32, 2, 16},  {64, 4, 16},   {100, 8, 16},  {128, 8, 16},  {160, 16, 16},
-    {256, 16, 16}, {512, 16, 32}, {1024, 32, 32}, {2048, 64, 32}, {65535, 64, 32}};
+    {16, 2, 8},   {32, 4, 8},   {64, 8, 8},    {100, 8, 13},  {128, 16, 8},  {160, 16, 10},
+    {256, 32, 8}, {512, 16, 32}, {1024, 32, 32}, {2048, 64, 32}, {65535, 64, 32}};
 
-int traceback_rows_cap(int cls) { return kTBShapes[cls].G * kTBShapes[cls].RPL; }
-int traceback_pairs_per_wave(int cls) { return 64 / kTBShapes[cls].G; }
 int traceback_waves_per_block() { return kWaves; }
 
 hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &sc,
@@ -406,12 +444,12 @@ hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &
     p.maxlen = maxlen;
     switch (cls) {
     case 0: return tb_launch<2, 8, false>(p, grid, st);
-    case 1: return tb_launch<2, 16, false>(p, grid, st);
-    case 2: return tb_launch<4, 16, false>(p, grid, st);
-    case 3: return tb_launch<8, 16, false>(p, grid, st);
-    case 4: return tb_launch<8, 16, false>(p, grid, st);
-    case 5: return tb_launch<16, 16, false>(p, grid, st);
-    case 6: return tb_launch<16, 16, false>(p, grid, st);
+    case 1: return tb_launch<4, 8, false>(p, grid, st);
+    case 2: return tb_launch<8, 8, false>(p, grid, st);
+    case 3: return tb_launch<8, 13, false>(p, grid, st);
+    case 4: return tb_launch<16, 8, false>(p, grid, st);
+    case 5: return tb_launch<16, 10, false>(p, grid, st);
+    case 6: return tb_launch<32, 8, false>(p, grid, st);
     case 7: return tb_launch<16, 32, false>(p, grid, st);
     case 8: return tb_launch<32, 32, false>(p, grid, st);
     case 9: return tb_launch<64, 32, false>(p, grid, st);
