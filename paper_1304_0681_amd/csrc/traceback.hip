@@ -407,7 +407,7 @@ hipError_t tb_launch(const TBParams &p, int grid, hipStream_t st)
 
 // Traceback shapes per query-length class (G lanes x RPL rows >= the class bound).
 static const ClassShape kTBShapes[kNumClasses] = {
-    {16, 2, 8},   {32, 4, 8},   {64, 8, 8},    {100, 8, 13},  {128, 16, 8},  {160, 16, 10},
+    {16, 2, 8},   {32, 4, 8},   {64, 8, 8},    {100, 8, 13},  {128, 16, 8},  {160, 8, 20},
     {256, 32, 8}, {512, 16, 32}, {1024, 32, 32}, {2048, 64, 32}, {65535, 64, 32}};
 
 int traceback_waves_per_block() { return kWaves; }
@@ -448,7 +448,7 @@ hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &
     case 2: return tb_launch<8, 8, false>(p, grid, st);
     case 3: return tb_launch<8, 13, false>(p, grid, st);
     case 4: return tb_launch<16, 8, false>(p, grid, st);
-    case 5: return tb_launch<16, 10, false>(p, grid, st);
+    case 5: return tb_launch<8, 20, false>(p, grid, st);
     case 6: return tb_launch<32, 8, false>(p, grid, st);
     case 7: return tb_launch<16, 32, false>(p, grid, st);
     case 8: return tb_launch<32, 32, false>(p, grid, st);
