@@ -243,11 +243,15 @@ def bench_filter(ctx, args, hard=False):
         "reads": b.n_reads, "pairs": b.n_pairs,
         "plain": {"ms_per_step": round(t_plain * 1e3, 3),
                   "reads_per_s": round(b.n_reads / t_plain, 1),
-                  "gcups": round(cells_all / t_plain / 1e9, 1)},
+                  "gcups": round(cells_all / t_plain / 1e9, 1),
+                  "gcups_frac_of_roofline": round(cells_all / t_plain / 1e9 / PEAK_GCUPS_INT16X2, 4)},
         "filtered": {"ms_per_step": round(t_filt * 1e3, 3),
                      "reads_per_s": round(b.n_reads / t_filt, 1),
                      "gcups_effective": round(cells_all / t_filt / 1e9, 1),
                      "gcups_dp": round(cells_kept / t_filt / 1e9, 1),
+                     # cells actually aligned per second of the whole filtered step,
+                     # as a fraction of the packed int16 SW roofline
+                     "gcups_dp_frac_of_roofline": round(cells_kept / t_filt / 1e9 / PEAK_GCUPS_INT16X2, 4),
                      "kept_pairs_fraction": round(float(keep.mean()), 5),
                      "unsure_reads_fraction": round(n_unsure / b.n_reads, 5)},
         "speedup_reads_per_s": round(t_plain / t_filt, 3),
@@ -292,6 +296,7 @@ def bench_spliced(ctx, args):
     db = sw.DeviceBatch.from_synth(ctx, b)
     ap = AlignPass(ctx, db, SCORING)
     s = torch.cuda.Stream()
+    sw.sw_timing_enable(ctx, False)          # graph capture records no timing events
     ap.capture(s)
     # eager pass with events between its phases (same stream)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
@@ -322,6 +327,7 @@ def bench_spliced(ctx, args):
     t_step = (time.perf_counter() - t1) / args.steps
     bp = ap.best_pair.cpu().numpy().view(np.uint32)
     aln = sw.aln_to_numpy(ap.aln)
+    filtered = None if args.no_filter else _spliced_filtered(ctx, args, b, db, ap, t_step)
     ok = bp < b.n_pairs
     m = b.read_len[b.windows["read_id"][bp[ok]]].astype(np.int64)
     n = np.minimum(b.windows["len"][bp[ok]].astype(np.int64),
@@ -344,7 +350,74 @@ def bench_spliced(ctx, args):
         "traceback_gcups": round(tb_cells / (phase[2] / 1e3) / 1e9, 1),
         "seeds_aligned": int(np.count_nonzero(aln["score"] > 0)),
         "generation_seconds": round(t_gen, 1),
+        "filtered": filtered,
     }
+
+
+def _spliced_filtered(ctx, args, b, db, ap, t_plain):
+    """The filtered form of the spliced pass: the network (trained and calibrated
+    on spliced seeds of other random seeds) picks the windows to align; the best
+    kept window of every seed is traced back.  Timed eagerly against the plain
+    pass's time; recall against its best scores."""
+    import torch
+
+    import paper_1304_0681_amd as sw
+    import synth
+    from paper_1304_0681_amd import train as tr
+
+    plain_best = ap.best_score.cpu().numpy()
+    sets = {}
+    for name, seed in (("train", synth.BASE_SEED + 33), ("cal", synth.BASE_SEED + 43)):
+        bb = synth.spliced(n_reads=40_000, seed=seed)
+        dbb = sw.DeviceBatch.from_synth(ctx, bb)
+        sets[name] = (bb, dbb, tr.plain_scores(ctx, dbb))
+    bb, dbb, pp = sets["train"]
+    feat, y = tr.features_and_labels(ctx, dbb, pp)
+    mlp, _ = tr.train(ctx, feat, y, steps=args.train_steps, batch=4096, seed=1)
+    feat, y_map = tr.features_and_labels(ctx, dbb, pp, min_best=T_MAP)
+    mlp_o, _ = tr.train(ctx, feat, y_map, steps=args.train_steps, batch=4096, seed=2)
+    del feat, y, y_map
+    bb, dbb, pp = sets["cal"]
+    f_ca, _ = tr.features_and_labels(ctx, dbb, pp)
+    sc_ca, best_ca = pp.hits[:, 0].cpu().numpy(), pp.best_score.cpu().numpy()
+    rid_ca = bb.windows["read_id"].astype(np.int64)
+    lo, hi, _ = tr.calibrate(tr.logits_of(ctx, mlp, f_ca).cpu().numpy(), sc_ca, best_ca, rid_ca,
+                             target=0.9995)
+    drop_o, lo_o, hi_o, _ = tr.calibrate_output(tr.logits_of(ctx, mlp_o, f_ca).cpu().numpy(), sc_ca,
+                                                best_ca, rid_ca, T_MAP, target=0.9995)
+    del f_ca, sets
+    buf = tr.FilterBuffers(b.n_pairs, b.n_reads)
+    mapped = plain_best >= T_MAP
+    out = {}
+    for rule, net, thr in (("strict", mlp, (float("-inf"), lo, hi)), ("output_level", mlp_o, (drop_o, lo_o, hi_o))):
+        def step():
+            db.pack_reads()
+            kept = tr.filtered_pass(ctx, net, db, thr[1], thr[2], buf, drop=thr[0])
+            sw.sw_batch_traceback(ctx, kept, SCORING, buf.best_pair, b.n_reads, ap.aln, ap.ops,
+                                  ap.ops_stride)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        fb = buf.best_score.cpu().numpy()
+        keep = buf.keep.cpu().numpy().astype(bool)
+        assert (fb <= plain_best).all()
+        out[rule] = {"ms_per_step": round(t * 1e3, 3), "reads_per_s": round(args.spliced_reads / t, 1),
+                     "speedup_over_plain_graph": round(t_plain / t, 3),
+                     "kept_pairs_fraction": round(float(keep.mean()), 5),
+                     "best_hit_recall": float((fb == plain_best).mean()),
+                     "best_hit_recall_mapped_seeds": float((fb[mapped] == plain_best[mapped]).mean()),
+                     "thresholds": list(thr)}
+    out["mapped_seeds_fraction"] = round(float(mapped.mean()), 5)
+    out["note"] = ("eager steps (encode, features, MLP, decision, compaction, SW on kept pairs, "
+                   "best window, traceback) against the plain pass replayed as a graph")
+    sw.sw_mlp_destroy(ctx, mlp)
+    sw.sw_mlp_destroy(ctx, mlp_o)
+    return out
 
 
 def bench_stream(ctx, args):
@@ -422,6 +495,9 @@ def bench_stream(ctx, args):
     wall = time.perf_counter() - t1
     mates = stats["mates"]
     pairs = sum(hcs[k % 2].n_pairs for k in range(n_chunks))
+    h2d = sum(hcs[k % 2].n_bases + 10 * hcs[k % 2].n_reads + 12 * hcs[k % 2].n_pairs
+              for k in range(n_chunks))
+    d2h = sum(hcs[k % 2].n_reads * (4 + 1 + 4 + 28 + 4 * 64) + 4 for k in range(n_chunks))
     sw.sw_mlp_destroy(ctx, mlp)
     return {
         "workload": f"paired reads: {n_chunks} chunks of {args.stream_frags} fragments "
@@ -433,6 +509,8 @@ def bench_stream(ctx, args):
         "fragments_per_s": round(mates / 2 / wall, 1),
         "ms_per_chunk": round(wall / n_chunks * 1e3, 3),
         "plain_sw_ms_per_chunk_device_resident": round(float(np.mean(plain_ms)), 3),
+        "host_to_device_gb": round(h2d / 1e9, 3), "device_to_host_gb": round(d2h / 1e9, 3),
+        "copy_gb_per_s_over_wall": round((h2d + d2h) / wall / 1e9, 2),
         "kept_pairs_fraction": round(stats["kept"] / pairs, 5),
         "best_hit_recall_mapped_mates": round(1 - stats["miss"] / max(stats["mapped"], 1), 6),
         "mapped_fraction": round(stats["mapped"] / mates, 5),
