@@ -1,19 +1,27 @@
 // Traceback: full alignments with CIGAR for selected pairs.
 //
 // The DP of the score kernel is recomputed with the same lane layout (G lanes
-// per pair, RPL rows per lane).  Every cell stores a
-// 4-bit direction code in a per-pair slot of device scratch:
-//   bits 0-1  H source: 0 stop (H == 0), 1 diagonal, 2 deletion (E), 3 insertion
-//             (first true in that order)
-//   bit 2     the deletion value of the NEXT column extends rather than opens
-//             (E(i,c) + gap_extend > H(i,c) + gap_open)
-//   bit 3     the insertion value of the NEXT row extends rather than opens
+// per pair, RPL rows per lane).  Every cell stores a 4-bit direction code in a
+// per-pair slot of device scratch, four comparison bits:
+//   bit 3  H(i,c) is not the diagonal value H(i-1,c-1) + s(i,c)
+//   bit 2  H(i,c) is not the deletion value E(i,c)
+//   bit 1  the deletion value of the NEXT column extends rather than opens
+//          (E(i,c) + gap_extend > H(i,c) + gap_open; an open wins ties)
+//   bit 0  the insertion value of the NEXT row extends rather than opens
+// Each bit is the sign of a difference, shifted into the lane's code word with
+// one funnel shift, so a cell costs no compare/select pairs.  The stop
+// condition (H == 0) needs no bit: every step of the walk fixes the value of
+// the cell it moves to (a diagonal step subtracts s(i,c), a gap step the
+// extension or opening penalty), so the walk knows H along the path and stops
+// where it reaches 0, which is the canonical rule (stop first, then diagonal,
+// deletion, insertion).
 // Column c stores its rows lane by lane: a lane's RPL rows fill ceil(RPL/8)
-// 32-bit words (8 codes each), so each lane writes whole words per step and a
-// tile needs no multiple of 8 rows per lane (104 rows cover 100-nt queries,
-// 160 rows 150-nt ones).  The first lane of each group then
-// walks back from the end cell (smallest window column, then smallest read row
-// among the maxima) under the canonical rule and run-length encodes the ops.
+// 32-bit words (8 codes each, the lane's first row in the highest nibble used),
+// so each lane writes whole words per step and a tile needs no multiple of 8
+// rows per lane (104 rows cover 100-nt queries, 160 rows 150-nt ones).  The
+// first lane of each group then walks back from the end cell (smallest window
+// column, then smallest read row among the maxima) and run-length encodes the
+// ops.
 #include "internal.h"
 
 namespace hpgsw {
@@ -68,6 +76,12 @@ __device__ __forceinline__ int tb_wave_max(int v)
     return v;
 }
 
+// (w << 1) | sign bit of x
+__device__ __forceinline__ uint32_t ins_sign(uint32_t w, int x)
+{
+    return __builtin_amdgcn_alignbit(w, (uint32_t)x, 31u);
+}
+
 __device__ __forceinline__ uint32_t tb_window_word(const TBParams &P, int64_t rb, int64_t c0)
 {
     const int64_t s = rb + c0;   // reference position of column c0
@@ -110,7 +124,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
     const uint64_t strips_max = STRIP ? (mmax + SR - 1) / SR : 1;
     const uint64_t slot_words = strips_max * G * WPL * nmax + (STRIP ? 2 * nmax : 0) + mmax + nmax + 8;
     const uint64_t fit = P.codes_words / ((uint64_t)PPW * slot_words);
-    const bool no_room = fit == 0;
+    // (a slot is addressed with 32-bit word offsets)
+    const bool no_room = fit == 0 || slot_words > 0xFFFFFFFFull;
     if (!no_room && wave_global >= fit)
         return;
     uint32_t *slot_codes = P.codes + (no_room ? 0 : (uint64_t)(wave_global * PPW + grp) * slot_words);
@@ -221,18 +236,22 @@ __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
                         diag = H[r];
                         const int e = E[r];
                         const int h = max(max(dd, e), g);
-                        const uint32_t src = h == 0 ? 0u : (h == dd ? 1u : (h == e ? 2u : 3u));
                         H[r] = h;
                         const int hg = h + go;
-                        const int en = max(e + ge, hg);
-                        const int gn = max(max(g + ge, hg), 0);
-                        // the next column's deletion / next row's insertion extends when its
-                        // new value is not the open value (an open wins ties); a clamped
-                        // insertion value (0) is never the source of a positive H
-                        const uint32_t ext = (en != hg ? 4u : 0u) | (gn != hg ? 8u : 0u);
+                        const int ege = e + ge, gge = g + ge;
+                        const int en = max(ege, hg);
+                        const int gn = max(max(gge, hg), 0);
+                        // code bits, most significant first (h >= dd and h >= e, so the
+                        // first two differences are negative exactly when h differs);
+                        // a clamped insertion value (0) is never the source of a
+                        // positive H, so its bit ignores the clamp
+                        uint32_t &cq = cw[r >> 3];
+                        cq = ins_sign(cq, dd - h);
+                        cq = ins_sign(cq, e - h);
+                        cq = ins_sign(cq, hg - ege);
+                        cq = ins_sign(cq, hg - gge);
                         E[r] = en;
                         g = gn;
-                        cw[r >> 3] |= (src | ext) << (4 * (r & 7));
                         cmax = max(cmax, h);
                     }
                     gout = g;
@@ -288,40 +307,92 @@ __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
                 a.read_begin = a.read_end = a.ref_begin = a.ref_end = -1;
                 a.n_ops = 0;
             } else {
-                // walk back; runs are collected last-to-first in `runs`
-                int i = rbest, c = cbest, state = 0, bi = rbest, bc = cbest;
+                // walk back; runs are collected last-to-first in `runs`; v is the
+                // value of the current state's matrix at (i, c)
+                int i = rbest, c = cbest, state = 0, bi = rbest, bc = cbest, v = best;
                 uint32_t nruns = 0, cur_op = 0xFFu, cur_len = 0;
                 // Most steps of the walk follow a diagonal (match runs), so a miss
-                // loads the code words of the next 8 cells of the diagonal at once
+                // loads the codes of the next 8 cells of the diagonal at once
                 // (independent loads; indices clamped into the slot, and a clamped
                 // entry is never asked for) and the following steps read registers.
-                uint32_t pw[8];
+                uint32_t pw[8];                              // codes, shifted down
                 int pi = -(1 << 30), pc = -(1 << 30);      // the diagonal held starts at (pi, pc)
-                // word of row ii within a column, and the row's code position in it
-                auto row_word = [&](int ii) -> uint32_t {
-                    const int sp = ii / SR, rs = ii - sp * SR, ln = rs / RPL, r = rs - ln * RPL;
-                    return (uint32_t)((sp * G + ln) * WPL + (r >> 3));
-                };
-                auto row_shift = [&](int ii) -> uint32_t { return 4u * (uint32_t)(((ii % SR) % RPL) & 7); };
                 auto code_at = [&](int ii, int cc) -> uint32_t {
                     const int k = pc - cc;
-                    uint32_t wv;
                     if (k >= 0 && k < 8 && pi - ii == k) {
-                        wv = pw[0];
+                        uint32_t cv = pw[0];
 #pragma unroll
                         for (int q = 1; q < 8; ++q)
-                            wv = k == q ? pw[q] : wv;
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) {
-                            const int c2 = max(cc - q, 0), i2 = max(ii - q, 0);
-                            pw[q] = slot_codes[(uint64_t)c2 * col_words + row_word(i2)];
-                        }
-                        pi = ii;
-                        pc = cc;
-                        wv = pw[0];
+                            cv = k == q ? pw[q] : cv;
+                        return cv;
                     }
-                    return (wv >> row_shift(ii)) & 15u;
+                    // lane-layout position of row ii (strip, lane, row in the lane);
+                    // each further entry is one row back (clamped at row 0)
+                    int sp = STRIP ? (int)((uint32_t)ii / (uint32_t)SR) : 0;
+                    const int rs = ii - sp * SR;
+                    int ln = (int)((uint32_t)rs / (uint32_t)RPL), r = rs - ln * RPL;
+                    uint32_t sh[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const uint32_t c2 = (uint32_t)max(cc - q, 0);
+                        pw[q] = slot_codes[c2 * col_words + (uint32_t)((sp * G + ln) * WPL + (r >> 3))];
+                        const int nq = min(8, RPL - (r & ~7));   // rows in the row's word
+                        sh[q] = 4u * (uint32_t)(nq - 1 - (r & 7));
+                        const bool at0 = ((STRIP ? sp : 0) | ln | r) == 0;
+                        const bool wrap = r == 0;
+                        r = at0 ? 0 : (wrap ? RPL - 1 : r - 1);
+                        ln = at0 ? 0 : (wrap ? ln - 1 : ln);
+                        if (STRIP) {
+                            const bool wrap2 = ln < 0;
+                            ln = wrap2 ? G - 1 : ln;
+                            sp = wrap2 ? sp - 1 : sp;
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        pw[q] = (pw[q] >> sh[q]) & 15u;
+                    pi = ii;
+                    pc = cc;
+                    return pw[0];
+                };
+                // substitution score of (ii, cc).  Positions are 32-bit offsets from
+                // the 16-base word holding the pair's first read base (first window
+                // base); the walk moves back one base at a time, so it holds the
+                // current word of the read and of the window and has the next word
+                // in the walk's direction in flight (clamped to the pair's words).
+                const uint32_t *rdw = P.reads + (roff >> 4);
+                const uint32_t *fww = P.ref + ((uint64_t)rb >> 4);
+                const uint32_t r0 = (uint32_t)(roff & 15), f0 = (uint32_t)((uint64_t)rb & 15);
+                const uint32_t rd_last = (r0 + (uint32_t)m - 1) >> 4;
+                auto read_pos = [&](int ii) -> uint32_t {
+                    return r0 + (uint32_t)(w.strand ? m - 1 - ii : ii);
+                };
+                auto read_next = [&](uint32_t wi) -> uint32_t {
+                    return w.strand ? min(wi + 1, rd_last) : (wi > 0 ? wi - 1 : 0u);
+                };
+                uint32_t rw_at = read_pos(i) >> 4, fw_at = (f0 + (uint32_t)c) >> 4;
+                uint32_t rw = rdw[rw_at], fw = fww[fw_at];
+                uint32_t rn_at = read_next(rw_at), fn_at = fw_at > 0 ? fw_at - 1 : 0u;
+                uint32_t rn = rdw[rn_at], fn = fww[fn_at];
+                auto subst = [&](int ii, int cc) -> int {
+                    const uint32_t pos = read_pos(ii), fpos = f0 + (uint32_t)cc;
+                    if ((pos >> 4) != rw_at) {
+                        rw_at = pos >> 4;
+                        rw = rw_at == rn_at ? rn : rdw[rw_at];
+                        rn_at = read_next(rw_at);
+                        rn = rdw[rn_at];
+                    }
+                    if ((fpos >> 4) != fw_at) {
+                        fw_at = fpos >> 4;
+                        fw = fw_at == fn_at ? fn : fww[fw_at];
+                        fn_at = fw_at > 0 ? fw_at - 1 : 0u;
+                        fn = fww[fn_at];
+                    }
+                    uint32_t q = (rw >> (2u * (pos & 15u))) & 3u;
+                    if (w.strand)
+                        q = 3u - q;
+                    const uint32_t f = (fw >> (2u * (fpos & 15u))) & 3u;
+                    return q == f ? P.ma : P.mi;
                 };
                 const uint32_t max_runs = (uint32_t)(m + n + 2);
                 auto emit = [&](uint32_t op) {
@@ -335,31 +406,32 @@ __global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
                     }
                 };
                 for (;;) {
+                    if (state == 0 && (i < 0 || c < 0 || v == 0))
+                        break;
+                    // one code per step: the cell itself (H), or the cell before it
+                    // in the gap's direction (the gap's extension bit); a gap that
+                    // reaches the matrix edge opens there
+                    const bool need = state == 0 || (state == 1 ? c > 0 : i > 0);
+                    const uint32_t code = need ? code_at(state == 2 ? i - 1 : i, state == 1 ? c - 1 : c) : 0u;
                     if (state == 0) {
-                        if (i < 0 || c < 0)
-                            break;
-                        const uint32_t src = code_at(i, c) & 3u;
-                        if (src == 0)
-                            break;
-                        if (src == 1) {
+                        if (!(code & 8u)) {             // diagonal
                             emit(SW_OP_M);
+                            v -= subst(i, c);
                             bi = i;
                             bc = c;
                             --i;
                             --c;
                         } else {
-                            state = (int)src - 1;   // 1: deletion run, 2: insertion run
+                            state = (code & 4u) ? 2 : 1;   // 1: deletion run, 2: insertion run
                         }
-                    } else if (state == 1) {
-                        emit(SW_OP_D);
-                        const uint32_t ext = c > 0 ? (code_at(i, c - 1) >> 2) & 1u : 0u;
-                        --c;
-                        if (!ext)
-                            state = 0;
                     } else {
-                        emit(SW_OP_I);
-                        const uint32_t ext = i > 0 ? (code_at(i - 1, c) >> 3) & 1u : 0u;
-                        --i;
+                        const uint32_t ext = state == 1 ? (code >> 1) & 1u : code & 1u;
+                        emit(state == 1 ? SW_OP_D : SW_OP_I);
+                        if (state == 1)
+                            --c;
+                        else
+                            --i;
+                        v -= ext ? ge : go;
                         if (!ext)
                             state = 0;
                     }
