@@ -48,12 +48,25 @@ SCORING = (5, -4, -10, -1)
 # On this workload a read against 16 random windows scores 91-146 (1st-99th
 # percentile, oracle on 3,000 reads) and a read against its origin 428-500.
 T_MAP = 200
-# VALU peak: 256 CUs x 64 lanes x 2.4 GHz = 39.3 T lane-instructions/s.  The
-# fixed algorithmic cost of one Gotoh cell is 10 int32 ops (3,932 GCUPS), or 11
-# packed int16 ops per 2 cells (7,149 GCUPS).
-VALU_LANE_OPS = 256 * 64 * 2.4e9
-PEAK_GCUPS_INT32 = VALU_LANE_OPS / 10 / 1e9
-PEAK_GCUPS_INT16X2 = VALU_LANE_OPS / 5.5 / 1e9
+# ALU rooflines.  1,024 SIMDs x 2.4 GHz; a wave64 VALU instruction occupies its
+# SIMD for 4 cycles, except 32-bit add/sub/logic/move, fp32 add/mul/fma and
+# 16-bit max, which take 2 (measured on gfx950 with independent register
+# chains).  The fixed algorithmic instruction mix of one Gotoh cell, costed at
+# those rates:
+#   packed int16, per 2 cells: table lookup, add, 2 max (H), saturating
+#     subtract (H + go), E and F (saturating subtract + max each), running max
+#     (10 four-cycle ops) and the selector xor (2 cycles): 42 cycles per 128
+#     cells -> 7,490 GCUPS
+#   int32, per cell: score select (4), diagonal add (2), H + go (2), E and F
+#     (add 2 + max 4 each), H max3 and the zero floor (4 + 4), running max (4):
+#     32 cycles per 64 cells -> 4,915 GCUPS
+#   traceback (int32 with 4 code bits per cell), per cell: the int32 recurrence
+#     (26 cycles with the running max as max3 over two rows), four differences
+#     (2 each) and four bit inserts (4 each): 50 cycles per 64 cells -> 3,146 GCUPS
+SIMD_CYCLES = 1024 * 2.4e9
+PEAK_GCUPS_INT16X2 = SIMD_CYCLES * 128 / 42 / 1e9
+PEAK_GCUPS_INT32 = SIMD_CYCLES * 64 / 32 / 1e9
+PEAK_GCUPS_TRACEBACK = SIMD_CYCLES * 64 / 50 / 1e9
 PATHS = {1: "int32", 2: "int32+ends", 3: "int16x2"}
 # HBM bytes per launch of the dominant kernel on the default workload, from two
 # rocprofv3 PMC runs (FETCH_SIZE, then WRITE_SIZE) of this script with
@@ -348,6 +361,7 @@ def bench_spliced(ctx, args):
                            "traceback": round(phase[2], 3)},
         "traceback_cells": tb_cells,
         "traceback_gcups": round(tb_cells / (phase[2] / 1e3) / 1e9, 1),
+        "traceback_frac_of_roofline": round(tb_cells / (phase[2] / 1e3) / 1e9 / PEAK_GCUPS_TRACEBACK, 4),
         "seeds_aligned": int(np.count_nonzero(aln["score"] > 0)),
         "generation_seconds": round(t_gen, 1),
         "filtered": filtered,
@@ -652,6 +666,13 @@ def main():
                  b.n_reads)),
             "kernel_ms": round(float(np.mean(score_ms)), 3),
             "frac_of_int32_roofline": round(kern_gcups / PEAK_GCUPS_INT32, 4),
+            # the same instruction mixes with every instruction at 4 cycles
+            # (11 packed ops per 2 cells, 10 int32 ops per cell)
+            "frac_at_4_cycles_per_instruction": round(
+                kern_gcups / ((PEAK_GCUPS_INT16X2 * 42 / 44) if path == "int16x2"
+                              else (PEAK_GCUPS_INT32 * 32 / 40)), 4),
+            "frac_of_int32_roofline_at_4_cycles_per_instruction": round(
+                kern_gcups / (PEAK_GCUPS_INT32 * 32 / 40), 4),
         },
     }
     if tune is not None:
