@@ -101,8 +101,10 @@ __device__ __forceinline__ uint32_t tb_window_word(const TBParams &P, int64_t rb
 
 // STRIP: queries longer than one strip of G*RPL rows (G == 64); the boundary
 // row between strips goes through the tail of the pair's slot.
+// The 20-row tile (150-nt queries) is held to 168 VGPRs for a third wave per SIMD,
+// which hides more of the walk; the other tiles already fit or would spill.
 template <int G, int RPL, bool STRIP>
-__global__ void __launch_bounds__(64 * kWaves) k_sw_traceback(const TBParams P)
+__global__ void __launch_bounds__(64 * kWaves, RPL == 20 ? 3 : 1) k_sw_traceback(const TBParams P)
 {
     constexpr int PPW = 64 / G;
     constexpr int SR = G * RPL;

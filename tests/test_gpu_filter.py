@@ -40,7 +40,8 @@ def test_features_bitexact(ctx):
 
 
 def test_features_edge_cases(ctx):
-    """Short reads (no 12-mer), short and clipped windows, both strands, repeats."""
+    """Short reads (no 12-mer), short and clipped windows, windows around the 1,024-base
+    feature limit and beyond it, both strands, repeats."""
     g = np.random.default_rng(8)
     refc = g.integers(0, 4, 20_000).astype(np.uint8)
     refc[5000:5300] = 0                                    # a homopolymer run
@@ -51,7 +52,9 @@ def test_features_edge_cases(ctx):
         reads.append(synth.ASCII[seg].tobytes())
         r = len(reads) - 1
         for (b0, n, st) in [(o - 20, 200, 0), (o, 11, 0), (o, 12, 1), (19_950, 400, 0),
-                            (5000, 280, 0), (int(g.integers(0, 19_000)), 600, 1)]:
+                            (5000, 280, 0), (int(g.integers(0, 19_000)), 600, 1),
+                            (o - 100, 1023, 0), (o - 200, 1024, 1), (o - 300, 1025, 0),
+                            (max(o - 900, 0), 2000, 1)]:
             wins.append((r, max(b0, 0), n, st))
     reads.append(synth.ASCII[np.zeros(90, np.uint8)].tobytes())      # poly-A read
     wins += [(len(reads) - 1, 4990, 400, 0), (len(reads) - 1, 100, 300, 1)]
@@ -64,6 +67,20 @@ def test_features_edge_cases(ctx):
     exp = bf16_bits(fr.batch_features(b))
     bad = np.nonzero((got != exp).any(axis=1))[0]
     assert len(bad) == 0, f"rows {bad[:5]} differ in cols {np.nonzero(got[bad[0]] != exp[bad[0]])[0]}"
+
+
+def test_features_bitexact_spliced_seeds(ctx):
+    """Spliced-read seeds: 100-nt seeds against 4-12 windows of 200-1,000 nt."""
+    b = synth.spliced(n_reads=120, seed=synth.BASE_SEED + 91, ref_len=2_000_000)
+    assert int(b.windows["len"].max()) >= 990
+    db = sw.DeviceBatch.from_synth(ctx, b)
+    feat = torch.zeros((b.n_pairs, 64), dtype=torch.int16, device="cuda")
+    sw.sw_features(ctx, db, feat)
+    torch.cuda.synchronize()
+    got = feat.cpu().numpy().view(np.uint16)
+    exp = bf16_bits(fr.batch_features(b))
+    bad = np.nonzero((got != exp).any(axis=1))[0]
+    assert len(bad) == 0, f"{len(bad)} rows differ, first {bad[:3]}"
 
 
 def _mlp(ctx, theta):
