@@ -206,6 +206,18 @@ def bench_filter(ctx, args, hard=False):
     plain_best = bs.cpu().numpy()
     plain_scores = hits[:, 0].cpu().numpy()
     t_filt = timed(filt_step)
+    # features alone, for their HBM rate: window words (first 1,024 bases),
+    # descriptor and feature row per candidate, read words, offset and length per read
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    f_ms = []
+    for _ in range(3):
+        ev[0].record()
+        sw.sw_features(ctx, db, buf.feat)
+        ev[1].record()
+        torch.cuda.synchronize()
+        f_ms.append(ev[0].elapsed_time(ev[1]))
+    wl = np.minimum(b.windows["len"].astype(np.int64), 1024)
+    f_bytes = float((wl / 4 + 12 + 128).sum()) + b.n_reads * (np.minimum(b.read_len, 256).mean() / 4 + 10)
     filt_best = buf.best_score.cpu().numpy()
     keep = buf.keep.cpu().numpy().astype(bool)
     n_unsure = int(buf.n_unsure.item())
@@ -266,7 +278,8 @@ def bench_filter(ctx, args, hard=False):
                      # as a fraction of the packed int16 SW roofline
                      "gcups_dp_frac_of_roofline": round(cells_kept / t_filt / 1e9 / PEAK_GCUPS_INT16X2, 4),
                      "kept_pairs_fraction": round(float(keep.mean()), 5),
-                     "unsure_reads_fraction": round(n_unsure / b.n_reads, 5)},
+                     "unsure_reads_fraction": round(n_unsure / b.n_reads, 5),
+                     "features": _rate(float(np.median(f_ms)), f_bytes)},
         "speedup_reads_per_s": round(t_plain / t_filt, 3),
         "best_hit_recall": recall,
         "best_hit_recall_mapped_reads": recall_map,
@@ -292,6 +305,11 @@ def bench_filter(ctx, args, hard=False):
                   "loss": [[s_, round(l_, 5)] for s_, l_ in losses]},
         "setup_seconds": round(time.perf_counter() - t0, 1),
     }
+
+
+def _rate(ms, nbytes):
+    return {"ms": round(ms, 4), "algorithmic_bytes": int(nbytes),
+            "gb_per_s": round(nbytes / (ms / 1e3) / 1e9, 1)}
 
 
 def bench_spliced(ctx, args):
@@ -615,6 +633,15 @@ def main():
         paths = list(tm.class_path[:])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # encode alone (events around it on the stream it runs on), for its HBM rate
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    enc_ms = []
+    for _ in range(5):
+        ev[0].record()
+        db.pack_reads()
+        ev[1].record()
+        torch.cuda.synchronize()
+        enc_ms.append(ev[0].elapsed_time(ev[1]))
     ms_step = elapsed / args.steps * 1e3
     gcups = cells / (ms_step / 1e3) / 1e9
     reads_s = b.n_reads / (ms_step / 1e3)
@@ -654,6 +681,13 @@ def main():
                    "reads": b.n_reads, "pairs": b.n_pairs, "cells": cells,
                    "form": "plain", "scoring": list(SCORING)},
         "reads_per_s": round(reads_s, 1),
+        # streaming phases of the step: algorithmic bytes (encode: ASCII read in, 2-bit
+        # words out; bucketing: descriptor, read length and offset gathered per pair,
+        # bin written and read back, pair id written) over the phase's time
+        "streaming_phases": {
+            "encode": _rate(float(np.median(enc_ms)), 1.25 * len(b.reads)),
+            "bucket": _rate(float(np.mean(bucket_ms)), 34.0 * b.n_pairs),
+        },
         "roofline": {
             "bound": "alu",
             "kernel": f"k_sw_score{'16' if path == 'int16x2' else ''} (query class {dom}, {path})",
