@@ -161,10 +161,18 @@ sw_status sw_best_per_read(sw_ctx *ctx, const sw_batch *batch, const sw_hit *d_h
  * junction search of task iv reads).  d_aln[n_sel] receives coordinates;
  * d_ops[n_sel * ops_stride] receives each pair's ops, soft clips included.
  * A pair whose CIGAR needs more than ops_stride ops gets the first
- * ops_stride ops and status bit0.  m + n + 2 ops always suffice. */
+ * ops_stride ops and status bit0.  m + n + 2 ops always suffice.
+ * d_hits (may be NULL): d_hits[n_pairs] as written by sw_batch_score with
+ * SW_WANT_ENDS for the same batch and scoring (indexed by pair, like
+ * d_pair_ids).  With it, each pair's DP covers only the window columns an
+ * alignment of that score ending at that cell can reach, which gives the same
+ * alignments and CIGARs in less time; pairs whose hit has no end, and every
+ * pair when a gap penalty is 0, use the whole window.  Hits that do not come
+ * from that call give undefined alignments (never out-of-bounds accesses). */
 sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *batch, const sw_scoring *sc,
                              const uint32_t *d_pair_ids, uint32_t n_sel, sw_aln *d_aln,
-                             uint32_t *d_ops, uint32_t ops_stride, void *stream);
+                             uint32_t *d_ops, uint32_t ops_stride, const sw_hit *d_hits,
+                             void *stream);
 
 /* Graph capture (the orchestration of a batch without per-call launch cost).
  * Every library call issued on `stream` between sw_graph_begin and

@@ -85,7 +85,7 @@ def lib() -> ctypes.CDLL:
                                      P, P]
         L.sw_best_per_read.argtypes = [P, ctypes.POINTER(sw_batch), P, I32, P, P, P, P]
         L.sw_batch_traceback.argtypes = [P, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scoring),
-                                         P, U32, P, P, U32, P]
+                                         P, U32, P, P, U32, P, P]
         L.sw_cigar_string.argtypes = [P, U32, ctypes.c_char_p, U32]
         L.sw_timing_enable.argtypes = [P, ctypes.c_int]
         L.sw_ctx_set_option.argtypes = [P, ctypes.c_int, ctypes.c_int]
@@ -167,10 +167,12 @@ def sw_best_per_read(ctx, batch, d_hits, t_map, d_best_pair, d_best_score, d_map
 
 
 def sw_batch_traceback(ctx, batch, scoring, d_pair_ids, n_sel, d_aln, d_ops, ops_stride,
-                       stream=None):
+                       stream=None, hits=None):
+    """`hits`: the batch's sw_batch_score results with SW_WANT_ENDS (optional; the
+    DP then covers only the columns each alignment can reach)."""
     _check(ctx, lib().sw_batch_traceback(ctx, ctypes.byref(batch.c), ctypes.byref(_sc(scoring)),
                                          _ptr(d_pair_ids), int(n_sel), _ptr(d_aln), _ptr(d_ops),
-                                         int(ops_stride), _stream_ptr(stream)))
+                                         int(ops_stride), _ptr(hits), _stream_ptr(stream)))
 
 
 def sw_ctx_set_option(ctx, option, value):

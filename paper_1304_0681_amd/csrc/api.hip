@@ -352,7 +352,8 @@ sw_status sw_best_per_read(sw_ctx *ctx, const sw_batch *b, const sw_hit *d_hits,
 
 sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc,
                              const uint32_t *d_pair_ids, uint32_t n_sel, sw_aln *d_aln,
-                             uint32_t *d_ops, uint32_t ops_stride, void *stream)
+                             uint32_t *d_ops, uint32_t ops_stride, const sw_hit *d_hits,
+                             void *stream)
 {
     if (!ctx)
         return fail(nullptr, SW_E_INVALID, "ctx is NULL");
@@ -390,7 +391,7 @@ sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *b, const sw_scoring *s
         HIP_TRY(ctx, launch_traceback_class(c, *b, *sc, d_pair_ids, bs.ids, bs.seg, bs.counter,
                                             d_aln, d_ops, ops_stride, ctx->tb,
                                             std::min(ctx->tb_bytes, ctx->tb_budget) / 4, bs.maxlen,
-                                            grid, s));
+                                            d_hits, grid, s));
     }
     return SW_OK;
 }

@@ -78,6 +78,7 @@ hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &
                                   const uint32_t *sel, const uint32_t *ids, const uint32_t *seg,
                                   uint32_t *counter, sw_aln *aln, uint32_t *ops,
                                   uint32_t ops_stride, uint32_t *codes, uint64_t codes_words,
-                                  const uint32_t *maxlen, int grid, hipStream_t st);
+                                  const uint32_t *maxlen, const sw_hit *hits, int grid,
+                                  hipStream_t st);
 
 }  // namespace hpgsw

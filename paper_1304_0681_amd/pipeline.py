@@ -12,17 +12,22 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (DeviceBatch, aln_to_numpy, sw_batch_score, sw_batch_traceback, sw_best_per_read,
-               sw_graph_begin, sw_graph_destroy, sw_graph_end, sw_graph_launch)
+from . import (SW_WANT_ENDS, DeviceBatch, aln_to_numpy, sw_batch_score, sw_batch_traceback,
+               sw_best_per_read, sw_graph_begin, sw_graph_destroy, sw_graph_end, sw_graph_launch)
 
 SCORING = (5, -4, -10, -1)
 
 
 class AlignPass:
+    """`band`: score with end cells and let the traceback's DP cover only the
+    columns each best alignment can reach (same results; pays where the reads
+    score on the int32 path, i.e. reads longer than 100 nt)."""
+
     def __init__(self, ctx, db: DeviceBatch, scoring=SCORING, t_map: int = 0,
-                 ops_stride: int | None = None):
+                 ops_stride: int | None = None, band: bool = False):
         import torch
         self.ctx, self.db, self.scoring, self.t_map = ctx, db, scoring, int(t_map)
+        self.band = bool(band)
         n_pairs, n_reads = db.n_pairs, db.n_reads
         if ops_stride is None:       # m + n + 2 ops always suffice
             ops_stride = db.read_len_max + db.window_len_max + 2
@@ -40,11 +45,13 @@ class AlignPass:
         """Encode (optional), score, best hit per read, traceback of the best hits."""
         if pack:
             self.db.pack_reads(stream)
-        sw_batch_score(self.ctx, self.db, self.scoring, 0, self.hits, stream)
+        sw_batch_score(self.ctx, self.db, self.scoring, SW_WANT_ENDS if self.band else 0, self.hits,
+                       stream)
         sw_best_per_read(self.ctx, self.db, self.hits, self.t_map, self.best_pair, self.best_score,
                          self.mapped, stream)
         sw_batch_traceback(self.ctx, self.db, self.scoring, self.best_pair, self.db.n_reads,
-                           self.aln, self.ops, self.ops_stride, stream)
+                           self.aln, self.ops, self.ops_stride, stream,
+                           hits=self.hits if self.band else None)
 
     def capture(self, stream, pack=True):
         """Record run() as a graph on `stream` (a created torch.cuda.Stream).  One

@@ -20,8 +20,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (ALN_DTYPE, WINDOW_DTYPE, _ptr, sw_batch, sw_batch_score, sw_batch_traceback,
-               sw_best_per_read, sw_filter_candidates, sw_pack2b)
+from . import (ALN_DTYPE, SW_WANT_ENDS, WINDOW_DTYPE, _ptr, sw_batch, sw_batch_score,
+               sw_batch_traceback, sw_best_per_read, sw_filter_candidates, sw_pack2b)
 
 SCORING = (5, -4, -10, -1)
 
@@ -96,15 +96,20 @@ class StreamAligner:
     """Filtered alignment of a stream of chunks against one resident reference.
 
     `thresholds` = (drop, lo, hi) of the filter's decision rule; `t_map` is the
-    mapping threshold of sw_best_per_read.  run() hands every chunk's results to
-    `consume(index, results)` as numpy arrays: best_score, mapped, pair (index of
-    the best window in the chunk's window list, -1 if none), aln, ops, kept
-    (pairs aligned)."""
+    mapping threshold of sw_best_per_read.  With `band` the kept pairs are scored
+    with their end cells and the traceback's DP covers only the columns each best
+    alignment can reach (same results; worth it when the reads score on the int32
+    path, i.e. reads longer than 100 nt, where ends cost about one instruction per
+    cell).  run() hands every chunk's results to `consume(index, results)` as numpy
+    arrays: best_score, mapped, pair (index of the best window in the chunk's
+    window list, -1 if none), aln, ops, kept (pairs aligned)."""
 
     def __init__(self, ctx, ref_ascii: np.ndarray, mlp, thresholds, t_map: int, reads_cap: int,
-                 bases_cap: int, pairs_cap: int, ops_stride: int = 64, scoring=SCORING):
+                 bases_cap: int, pairs_cap: int, ops_stride: int = 64, scoring=SCORING,
+                 band: bool = True):
         import torch
         self.ctx, self.mlp, self.scoring, self.t_map = ctx, mlp, scoring, int(t_map)
+        self.band = bool(band)
         self.drop, self.lo, self.hi = (float(x) for x in thresholds)
         self.ops_stride = int(ops_stride)
         self.caps = (reads_cap, bases_cap, pairs_cap)
@@ -133,11 +138,11 @@ class StreamAligner:
         sw_filter_candidates(self.ctx, full, self.mlp, self.lo, self.hi, ds.feat, ds.logits, ds.keep,
                              ds.win_out, ds.sel, ds.n_sel, ds.n_unsure, s, logit_drop=self.drop)
         kept = self._batch(ds, hc, ds.win_out, ds.n_sel)
-        sw_batch_score(self.ctx, kept, self.scoring, 0, ds.hits, s)
+        sw_batch_score(self.ctx, kept, self.scoring, SW_WANT_ENDS if self.band else 0, ds.hits, s)
         sw_best_per_read(self.ctx, kept, ds.hits, self.t_map, ds.best_pair, ds.best_score,
                          ds.mapped, s)
         sw_batch_traceback(self.ctx, kept, self.scoring, ds.best_pair, hc.n_reads, ds.aln, ds.ops,
-                           self.ops_stride, s)
+                           self.ops_stride, s, hits=ds.hits if self.band else None)
         # index of the best window in the chunk's own window list (data movement only)
         n = hc.n_reads
         bp = ds.best_pair[:n].long()

@@ -31,8 +31,14 @@ def gpu_score(ctx, b, sc=SC, ends=True, db=None):
     return sw.hits_to_numpy(hits)
 
 
-def gpu_traceback(ctx, b, sel=None, sc=SC, stride=None, db=None):
+def gpu_traceback(ctx, b, sel=None, sc=SC, stride=None, db=None, band=False):
+    """band: pass the score kernel's hits (with ends) so that each DP covers only
+    the columns the alignment can reach."""
     db = db or sw.DeviceBatch.from_synth(ctx, b)
+    hits = None
+    if band:
+        hits = torch.full((b.n_pairs, 3), -7, dtype=torch.int32, device="cuda")
+        sw.sw_batch_score(ctx, db, sc, sw.SW_WANT_ENDS, hits)
     if sel is None:
         sel = np.arange(b.n_pairs, dtype=np.uint32)
     sel = np.asarray(sel, dtype=np.uint32)
@@ -41,7 +47,7 @@ def gpu_traceback(ctx, b, sel=None, sc=SC, stride=None, db=None):
     ids = torch.from_numpy(sel.view(np.int32)).cuda()
     aln = torch.full((len(sel), 7), -7, dtype=torch.int32, device="cuda")
     ops = torch.zeros((len(sel), stride), dtype=torch.int32, device="cuda")
-    sw.sw_batch_traceback(ctx, db, sc, ids, len(sel), aln, ops, stride)
+    sw.sw_batch_traceback(ctx, db, sc, ids, len(sel), aln, ops, stride, hits=hits)
     torch.cuda.synchronize()
     return sw.aln_to_numpy(aln), ops.cpu().numpy().view(np.uint32)
 
@@ -143,6 +149,37 @@ def test_edge_lengths_traceback(ctx):
     ref, rops = oracle.align_batch(b, SC, mode=1)
     a, o = gpu_traceback(ctx, b)
     assert_aln_equal(a, o, ref, rops)
+
+
+@pytest.mark.parametrize("sc", [(5, -4, -10, -1), (2, -3, -4, -4), (1, 0, -2, -1),
+                                (127, -127, -127, 0), (5, -4, -10, -10)])
+def test_traceback_band_from_score_ends(ctx, sc):
+    """Traceback restricted to the columns an alignment of the pair's score and end
+    can reach gives the oracle's alignments (edge lengths over every class; a gap
+    extension of 0 makes the band the whole window)."""
+    b = edge_batch(13, EDGE_M, EDGE_N)
+    ref, rops = oracle.align_batch(b, sc, mode=1)
+    a, o = gpu_traceback(ctx, b, sc=sc, band=True)
+    assert_aln_equal(a, o, ref, rops)
+
+
+def test_traceback_band_paired_mates(ctx):
+    """150-nt mates against 16 windows of 200-1,000 nt (the stream's shape): best
+    window per mate traced with and without the band, both equal to the oracle."""
+    ref_codes = synth.make_reference(synth.rng(synth.BASE_SEED + 61), 400_000)
+    b = synth.paired_chunk(synth.BASE_SEED + 62, 150, ref_codes)
+    h = oracle.align_batch(b, SC, mode=0)[0]
+    rid = b.windows["read_id"].astype(np.int64)
+    best = np.full(b.n_reads, -1, dtype=np.int64)
+    for k in np.argsort(-h["score"], kind="stable"):
+        if best[rid[k]] < 0:
+            best[rid[k]] = k
+    sel = best[best >= 0].astype(np.uint32)
+    ref, rops = oracle.align_batch(b, SC, mode=1, sel=sel)
+    db = sw.DeviceBatch.from_synth(ctx, b)
+    for band in (False, True):
+        a, o = gpu_traceback(ctx, b, sel=sel, db=db, band=band, stride=int(rops.shape[1]))
+        assert_aln_equal(a, o, ref, rops)
 
 
 @pytest.mark.parametrize("sc", [(2, -3, -4, -4), (1, 0, -2, -1), (3, -1, -5, -2), (127, -127, -127, 0),
