@@ -373,7 +373,8 @@ sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *b, const sw_scoring *s
     BucketScratch bs;
     if ((st = bucket_scratch(ctx, n_sel, &bs)))
         return st;
-    HIP_TRY(ctx, launch_bucket(*b, d_pair_ids, n_sel, bs, nullptr, d_aln, s));
+    const TbBand band{d_hits, sc->match, -sc->gap_open, -sc->gap_extend};
+    HIP_TRY(ctx, launch_bucket(*b, d_pair_ids, n_sel, bs, nullptr, d_aln, s, band));
     // Code slots come from a fixed scratch budget; every class kernel sizes its
     // slots from the class maxima on the device and runs the waves that fit, so
     // the call needs no host round trip and can be captured in a graph.
@@ -391,7 +392,7 @@ sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *b, const sw_scoring *s
         HIP_TRY(ctx, launch_traceback_class(c, *b, *sc, d_pair_ids, bs.ids, bs.seg, bs.counter,
                                             d_aln, d_ops, ops_stride, ctx->tb,
                                             std::min(ctx->tb_bytes, ctx->tb_budget) / 4, bs.maxlen,
-                                            d_hits, grid, s));
+                                            band, grid, s));
     }
     return SW_OK;
 }

@@ -50,8 +50,8 @@ __device__ __forceinline__ void trivial(uint32_t k, int score, sw_hit *hits, sw_
 }
 
 __device__ __forceinline__ uint32_t pair_bin(const sw_batch &b, const uint32_t *sel, uint32_t k,
-                                             sw_hit *hits, sw_aln *aln, uint32_t &n_out,
-                                             uint32_t &m_out)
+                                             sw_hit *hits, sw_aln *aln, const TbBand &band,
+                                             uint32_t &n_out, uint32_t &m_out)
 {
     const uint32_t p = sel ? sel[k] : k;
     n_out = 0;
@@ -79,6 +79,10 @@ __device__ __forceinline__ uint32_t pair_bin(const sw_batch &b, const uint32_t *
         trivial(k, 0, hits, aln);
         return kNone;
     }
+    if (aln) {      // traceback: the width its DP covers
+        int c_lo;
+        n = (uint32_t)tb_band(band, p, (int)m, (int)n, c_lo);
+    }
     n_out = n;
     m_out = m;
     return (uint32_t)class_of((int)m) * kBinsPerClass + len_bin(n);
@@ -94,7 +98,8 @@ __global__ void __launch_bounds__(kBlock) k_zero(uint32_t *hist, uint32_t *maxle
 
 __global__ void __launch_bounds__(kBlock) k_classify(sw_batch b, const uint32_t *sel, uint32_t n_items,
                                                      uint32_t *bin_out, uint32_t *hist,
-                                                     uint32_t *maxlen, sw_hit *hits, sw_aln *aln)
+                                                     uint32_t *maxlen, sw_hit *hits, sw_aln *aln,
+                                                     TbBand band)
 {
     __shared__ uint32_t lh[kNumBins];
     __shared__ uint32_t lmax[2 * kNumClasses];
@@ -111,7 +116,7 @@ __global__ void __launch_bounds__(kBlock) k_classify(sw_batch b, const uint32_t 
         if (p >= n_items)
             break;
         uint32_t n = 0, m = 0;
-        const uint32_t bin = pair_bin(b, sel, (uint32_t)p, hits, aln, n, m);
+        const uint32_t bin = pair_bin(b, sel, (uint32_t)p, hits, aln, band, n, m);
         bin_out[p] = bin;
         if (bin != kNone) {
             atomicAdd(&lh[bin], 1u);
@@ -203,14 +208,15 @@ __global__ void __launch_bounds__(kBlock) k_scatter(uint32_t n_pairs, const uint
 }  // namespace
 
 hipError_t launch_bucket(const sw_batch &b, const uint32_t *sel, uint32_t n_items,
-                         const BucketScratch &s, sw_hit *hits, sw_aln *aln, hipStream_t st)
+                         const BucketScratch &s, sw_hit *hits, sw_aln *aln, hipStream_t st,
+                         const TbBand &band)
 {
     hipLaunchKernelGGL(k_zero, dim3(64), dim3(kBlock), 0, st, s.hist, s.maxlen);
     const uint64_t per_block = (uint64_t)kBlock * kItems;
     const unsigned blocks = (unsigned)((n_items + per_block - 1) / per_block);
     if (n_items)
         hipLaunchKernelGGL(k_classify, dim3(blocks), dim3(kBlock), 0, st, b, sel, n_items, s.bin,
-                           s.hist, s.maxlen, hits, aln);
+                           s.hist, s.maxlen, hits, aln, band);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, s.hist, s.seg, s.counter);
     if (n_items)
         hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(kBlock), 0, st, n_items,

@@ -41,6 +41,39 @@ struct BucketScratch {
     uint32_t *maxlen;    // [2 * kNumClasses] longest window, then longest read, per class
 };
 
+// Traceback band: with a pair's score S and canonical end (i_e, c_e) from the
+// score pass, the alignment uses M <= i_e + 1 aligned rows and D deletions with
+// S <= match * M - (cost of D deletions); a run of L deletions costs
+// go + (L - 1) ge (penalties as positive numbers), so D deletions cost at least
+// go + (D - 1) ge when go >= ge and D go otherwise.  The alignment therefore
+// lies in window columns [c_e + 1 - (i_e + 1) - D_max, c_e].  The DP over those
+// columns gives every cell of the canonical path, and every value compared
+// there, the value of the full DP (a band only removes paths, and each path
+// cell's best prefix lies inside it), so codes, end and walk are unchanged.
+struct TbBand {
+    const sw_hit *hits;    // per pair, or null: no band
+    int ma, go, ge;        // match score, gap open and extension penalties (> 0)
+};
+
+// Width of the pair's DP window (n without a band) and its first column.
+__device__ __forceinline__ int tb_band(const TbBand &bd, uint32_t pair, int m, int n, int &c_lo)
+{
+    c_lo = 0;
+    if (!bd.hits || bd.go <= 0 || bd.ge <= 0 || bd.ma <= 0)
+        return n;
+    const sw_hit h = bd.hits[pair];
+    if (h.score <= 0 || h.read_end < 0 || h.read_end >= m || h.ref_end < 0 || h.ref_end >= n)
+        return n;
+    const int64_t rows = (int64_t)h.read_end + 1;
+    const int64_t slack = (int64_t)bd.ma * rows - h.score;
+    int64_t dmax = 0;
+    if (slack > 0)
+        dmax = bd.go >= bd.ge ? (slack < bd.go ? 0 : (slack - bd.go) / bd.ge + 1) : slack / bd.go;
+    const int64_t lo = (int64_t)h.ref_end + 1 - (rows + dmax);
+    c_lo = lo > 0 ? (int)lo : 0;
+    return h.ref_end + 1 - c_lo;
+}
+
 struct ScoreParams {
     const uint32_t *ref;
     uint64_t ref_len;
@@ -63,8 +96,11 @@ struct ScoreParams {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_pack2b(const uint8_t *ascii, uint64_t n, uint32_t *out, uint32_t *bad,
                          hipStream_t st);
+// Traceback pairs (aln != null) are binned by the width of their DP window,
+// the band when `band.hits` is given.
 hipError_t launch_bucket(const sw_batch &b, const uint32_t *sel, uint32_t n_items,
-                         const BucketScratch &s, sw_hit *hits, sw_aln *aln, hipStream_t st);
+                         const BucketScratch &s, sw_hit *hits, sw_aln *aln, hipStream_t st,
+                         const TbBand &band = TbBand{nullptr, 0, 0, 0});
 hipError_t launch_score_class(int cls, int G, int RPL, int mode, const ScoreParams &p, int grid,
                               hipStream_t st);
 int score_class_m_max(int cls);
@@ -78,7 +114,7 @@ hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &
                                   const uint32_t *sel, const uint32_t *ids, const uint32_t *seg,
                                   uint32_t *counter, sw_aln *aln, uint32_t *ops,
                                   uint32_t ops_stride, uint32_t *codes, uint64_t codes_words,
-                                  const uint32_t *maxlen, const sw_hit *hits, int grid,
+                                  const uint32_t *maxlen, const TbBand &band, int grid,
                                   hipStream_t st);
 
 }  // namespace hpgsw

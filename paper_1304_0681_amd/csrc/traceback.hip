@@ -50,8 +50,7 @@ struct TBParams {
     uint32_t *codes;           // scratch holding one slot per pair in flight
     uint64_t codes_words;      // size of the scratch in 32-bit words
     const uint32_t *maxlen;    // per class: longest window, then longest read
-    const sw_hit *hits;        // scores and ends of the batch's pairs, or null
-    int gmin;                  // min(-gap_open, -gap_extend)
+    TbBand band;               // score-pass hits for the DP band (hits may be null)
 };
 
 template <int G>
@@ -158,27 +157,8 @@ __global__ void __launch_bounds__(64 * kWaves, RPL == 20 ? 3 : 1) k_sw_traceback
             roff = P.read_off[w.read_id];
             const uint64_t avail = P.ref_len - w.ref_begin;
             n = w.len < avail ? (int)w.len : (int)avail;
-            if (P.hits) {
-                // With the pair's score S and canonical end (i_e, c_e) known, the
-                // alignment uses at most M <= i_e + 1 aligned rows and D deletions,
-                // and S <= match * M - gmin * D (gmin: the cheaper gap penalty per
-                // base), so it spans at most (i_e + 1) + (match (i_e + 1) - S) / gmin
-                // columns ending at c_e.  The DP over that band only gives every cell
-                // of the canonical path, and every value its codes compare against on
-                // the path, the same value as the full DP (a band only removes paths,
-                // and each path cell's best prefix lies inside it), so codes, end and
-                // walk are unchanged.
-                const sw_hit h = P.hits[pair];
-                if (P.gmin > 0 && h.score > 0 && h.read_end >= 0 && h.read_end < m &&
-                    h.ref_end >= 0 && h.ref_end < n) {
-                    const int64_t rows = (int64_t)h.read_end + 1;
-                    const int64_t slack = (int64_t)P.ma * rows - h.score;
-                    const int64_t span = rows + (slack > 0 ? slack / P.gmin : 0);
-                    const int64_t lo = (int64_t)h.ref_end + 1 - span;
-                    c_lo = lo > 0 ? (int)lo : 0;
-                    n = h.ref_end + 1 - c_lo;
-                }
-            }
+            // the band the bucketing kernel binned the pair by (same function)
+            n = tb_band(P.band, pair, m, n, c_lo);
         }
         const int n_wave = tb_wave_max(n);
         const int T = n_wave + G - 1;
@@ -513,7 +493,7 @@ hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &
                                   const uint32_t *sel, const uint32_t *ids, const uint32_t *seg,
                                   uint32_t *counter, sw_aln *aln, uint32_t *ops,
                                   uint32_t ops_stride, uint32_t *codes, uint64_t codes_words,
-                                  const uint32_t *maxlen, const sw_hit *hits, int grid,
+                                  const uint32_t *maxlen, const TbBand &band, int grid,
                                   hipStream_t st)
 {
     TBParams p;
@@ -540,8 +520,7 @@ hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &
     p.codes = codes;
     p.codes_words = codes_words;
     p.maxlen = maxlen;
-    p.hits = hits;
-    p.gmin = std::min(-sc.gap_open, -sc.gap_extend);
+    p.band = band;
     switch (cls) {
     case 0: return tb_launch<2, 8, false>(p, grid, st);
     case 1: return tb_launch<4, 8, false>(p, grid, st);
