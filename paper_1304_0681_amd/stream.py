@@ -13,8 +13,11 @@ of reads (with all of their candidate windows) is one batch.  Each chunk is:
 
 Two device buffer sets and three streams (host-to-device copies, compute,
 device-to-host copies) overlap the copies of chunks i + 1 and i - 1 with the
-compute of chunk i.  The reference stays resident (packed once); host buffers
-are pinned allocations so that the copies are asynchronous.
+compute of chunk i.  The results of chunk i - 1 are copied out once chunk i has
+passed its filter stage, so that those copies (kernels writing to host memory)
+run beside the arithmetic-bound scoring instead of the memory-bound filter
+kernels they would slow down.  The reference stays resident (packed once); host
+buffers are pinned allocations so that the copies are asynchronous.
 """
 from __future__ import annotations
 
@@ -75,6 +78,7 @@ class _DeviceSet:
         self.ops = torch.empty((reads_cap, ops_stride), dtype=torch.int32, device=d)
         self.pair = torch.empty(reads_cap, dtype=torch.int32, device=d)
         self.h2d = torch.cuda.Event()
+        self.filtered = torch.cuda.Event()   # the chunk's filter stage has finished
         self.done = torch.cuda.Event()
         self.free = None           # event after which the set may be overwritten
 
@@ -138,6 +142,7 @@ class StreamAligner:
         sw_filter_candidates(self.ctx, full, self.mlp, self.lo, self.hi, ds.feat, ds.logits, ds.keep,
                              ds.win_out, ds.sel, ds.n_sel, ds.n_unsure, s, logit_drop=self.drop)
         kept = self._batch(ds, hc, ds.win_out, ds.n_sel)
+        ds.filtered.record(s)
         sw_batch_score(self.ctx, kept, self.scoring, SW_WANT_ENDS if self.band else 0, ds.hits, s)
         sw_best_per_read(self.ctx, kept, ds.hits, self.t_map, ds.best_pair, ds.best_score,
                          ds.mapped, s)
@@ -159,15 +164,33 @@ class StreamAligner:
                           kept=int(ho.n_sel[0])))
         ho.pending = None
 
+    def _copy_out(self, ds, ho, idx, n, after=None):
+        """Device -> host copy of a computed chunk's results (on the d2h stream)."""
+        import torch
+        self.s_d2h.wait_event(ds.done)
+        if after is not None:
+            self.s_d2h.wait_event(after)
+        with torch.cuda.stream(self.s_d2h):
+            ho.best_score[:n].copy_(ds.best_score[:n], non_blocking=True)
+            ho.mapped[:n].copy_(ds.mapped[:n], non_blocking=True)
+            ho.pair[:n].copy_(ds.pair[:n], non_blocking=True)
+            ho.aln[:n].copy_(ds.aln[:n], non_blocking=True)
+            ho.ops[:n].copy_(ds.ops[:n], non_blocking=True)
+            ho.n_sel.copy_(ds.n_sel, non_blocking=True)
+            ho.d2h.record(self.s_d2h)
+        ho.pending = (idx, n)
+        ds.free = ho.d2h
+
     def run(self, chunks, consume=None):
         """Process the HostChunk sequence `chunks` in order."""
         import torch
         consume = consume or (lambda i, r: None)
         rc, bc, pc = self.caps
+        prev = None            # (device set, chunk index, reads) computed, not yet copied out
         for i, hc in enumerate(chunks):
             if hc.n_reads > rc or hc.n_bases > bc or hc.n_pairs > pc:
                 raise ValueError("chunk exceeds the stream's capacity")
-            ds, ho = self.sets[i % 2], self.outs[i % 2]
+            ds = self.sets[i % 2]
             # host -> device, once the set's previous chunk has been copied out
             if ds.free is not None:
                 self.s_h2d.wait_event(ds.free)
@@ -181,21 +204,20 @@ class StreamAligner:
             with torch.cuda.stream(self.s_comp):
                 self._compute(ds, hc)
                 ds.done.record(self.s_comp)
-            # the pinned output set still holds chunk i - 2: hand it out first
+            if prev is not None:
+                pds, pidx, pn = prev
+                ho = self.outs[pidx % 2]
+                # the pinned output set still holds chunk pidx - 2: hand it out first
+                if ho.pending is not None:
+                    self._hand_out(ho, consume)
+                self._copy_out(pds, ho, pidx, pn, after=ds.filtered)
+            prev = (ds, i, hc.n_reads)
+        if prev is not None:
+            pds, pidx, pn = prev
+            ho = self.outs[pidx % 2]
             if ho.pending is not None:
                 self._hand_out(ho, consume)
-            self.s_d2h.wait_event(ds.done)
-            n = hc.n_reads
-            with torch.cuda.stream(self.s_d2h):
-                ho.best_score[:n].copy_(ds.best_score[:n], non_blocking=True)
-                ho.mapped[:n].copy_(ds.mapped[:n], non_blocking=True)
-                ho.pair[:n].copy_(ds.pair[:n], non_blocking=True)
-                ho.aln[:n].copy_(ds.aln[:n], non_blocking=True)
-                ho.ops[:n].copy_(ds.ops[:n], non_blocking=True)
-                ho.n_sel.copy_(ds.n_sel, non_blocking=True)
-                ho.d2h.record(self.s_d2h)
-            ho.pending = (i, n)
-            ds.free = ho.d2h
+            self._copy_out(pds, ho, pidx, pn)
         for k in range(len(chunks), len(chunks) + 2):
             ho = self.outs[k % 2]
             if ho.pending is not None:
