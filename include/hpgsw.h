@@ -156,6 +156,15 @@ sw_status sw_best_per_read(sw_ctx *ctx, const sw_batch *batch, const sw_hit *d_h
                            int32_t t_map, uint32_t *d_best_pair, int32_t *d_best_score,
                            uint8_t *d_mapped, void *stream);
 
+/* d_win_out[k] = the window of pair d_pair_ids[k] of `batch`, for k < n (ids
+ * at or beyond the batch's pairs give a window with read id 0xFFFFFFFF, which
+ * every call answers as an invalid pair).  With the ids from
+ * sw_best_per_read this builds a batch of each read's best window, which can
+ * be scored with SW_WANT_ENDS and traced back with those hits (the traceback's
+ * band) at the cost of one pass over the best windows only. */
+sw_status sw_select_windows(sw_ctx *ctx, const sw_batch *batch, const uint32_t *d_pair_ids,
+                            uint32_t n, sw_window *d_win_out, void *stream);
+
 /* Full alignments with CIGAR for the pairs listed in d_pair_ids[n_sel]
  * (Sec. 2, stage E task iii: the alignment and its start position, which the
  * junction search of task iv reads).  d_aln[n_sel] receives coordinates;

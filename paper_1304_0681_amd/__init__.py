@@ -86,6 +86,7 @@ def lib() -> ctypes.CDLL:
         L.sw_best_per_read.argtypes = [P, ctypes.POINTER(sw_batch), P, I32, P, P, P, P]
         L.sw_batch_traceback.argtypes = [P, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scoring),
                                          P, U32, P, P, U32, P, P]
+        L.sw_select_windows.argtypes = [P, ctypes.POINTER(sw_batch), P, U32, P, P]
         L.sw_cigar_string.argtypes = [P, U32, ctypes.c_char_p, U32]
         L.sw_timing_enable.argtypes = [P, ctypes.c_int]
         L.sw_ctx_set_option.argtypes = [P, ctypes.c_int, ctypes.c_int]
@@ -109,7 +110,7 @@ def lib() -> ctypes.CDLL:
         L.sw_graph_launch.argtypes = [P, P, P]
         L.sw_graph_destroy.argtypes = [P, P]
         for f in ("sw_ctx_create", "sw_ctx_destroy", "sw_pack2b", "sw_batch_score",
-                  "sw_best_per_read", "sw_batch_traceback", "sw_cigar_string",
+                  "sw_best_per_read", "sw_batch_traceback", "sw_select_windows", "sw_cigar_string",
                   "sw_timing_enable", "sw_timing_get", "sw_ctx_set_option", "sw_mlp_create",
                   "sw_graph_begin", "sw_graph_end", "sw_graph_launch", "sw_graph_destroy",
                   "sw_autotune",
@@ -164,6 +165,11 @@ def sw_best_per_read(ctx, batch, d_hits, t_map, d_best_pair, d_best_score, d_map
     _check(ctx, lib().sw_best_per_read(ctx, ctypes.byref(batch.c), _ptr(d_hits), int(t_map),
                                        _ptr(d_best_pair), _ptr(d_best_score), _ptr(d_mapped),
                                        _stream_ptr(stream)))
+
+
+def sw_select_windows(ctx, batch, d_pair_ids, n, d_win_out, stream=None):
+    _check(ctx, lib().sw_select_windows(ctx, ctypes.byref(batch.c), _ptr(d_pair_ids), int(n),
+                                        _ptr(d_win_out), _stream_ptr(stream)))
 
 
 def sw_batch_traceback(ctx, batch, scoring, d_pair_ids, n_sel, d_aln, d_ops, ops_stride,

@@ -350,6 +350,23 @@ sw_status sw_best_per_read(sw_ctx *ctx, const sw_batch *b, const sw_hit *d_hits,
     return SW_OK;
 }
 
+sw_status sw_select_windows(sw_ctx *ctx, const sw_batch *b, const uint32_t *d_pair_ids,
+                            uint32_t n, sw_window *d_win_out, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    sw_status st = check_batch(ctx, b);
+    if (st)
+        return st;
+    if (n == 0)
+        return SW_OK;
+    if (!d_pair_ids || !d_win_out)
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_select_windows(*b, d_pair_ids, n, d_win_out, static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
 sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc,
                              const uint32_t *d_pair_ids, uint32_t n_sel, sw_aln *d_aln,
                              uint32_t *d_ops, uint32_t ops_stride, const sw_hit *d_hits,

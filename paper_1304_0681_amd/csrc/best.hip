@@ -48,6 +48,23 @@ __global__ void __launch_bounds__(256) k_best_final(uint32_t n_reads, const uint
     }
 }
 
+// out[k] = win[ids[k]]; an id outside the batch gives a window with an invalid
+// read id, which every later call answers as an invalid pair
+__global__ void __launch_bounds__(256) k_select_windows(uint32_t n, const uint32_t *ids,
+                                                        const sw_window *win, uint32_t n_pairs,
+                                                        const uint32_t *d_n, sw_window *out)
+{
+    if (d_n)
+        n_pairs = min(n_pairs, *d_n);
+    for (uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (uint64_t)gridDim.x * 256) {
+        const uint32_t p = ids[k];
+        sw_window w{0xFFFFFFFFu, 0u, 0u, 0u, 0u};
+        if (p < n_pairs)
+            w = win[p];
+        out[k] = w;
+    }
+}
+
 unsigned grid_for(uint64_t n)
 {
     uint64_t b = (n + 255) / 256;
@@ -67,6 +84,15 @@ hipError_t launch_best(const sw_batch &b, const sw_hit *hits, uint64_t *keys, in
                            b.d_n_pairs, b.d_win, hits, b.n_reads, keys);
     hipLaunchKernelGGL(k_best_final, dim3(grid_for(b.n_reads)), dim3(256), 0, st, b.n_reads, keys,
                        t_map, best_pair, best_score, mapped);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_windows(const sw_batch &b, const uint32_t *ids, uint32_t n, sw_window *out,
+                                 hipStream_t st)
+{
+    if (n)
+        hipLaunchKernelGGL(k_select_windows, dim3(grid_for(n)), dim3(256), 0, st, n, ids, b.d_win,
+                           b.n_pairs, b.d_n_pairs, out);
     return hipGetLastError();
 }
 

@@ -109,6 +109,8 @@ bool score_shape_available(int G, int RPL);
 int score_waves_per_block();
 hipError_t launch_best(const sw_batch &b, const sw_hit *hits, uint64_t *keys, int32_t t_map,
                        uint32_t *best_pair, int32_t *best_score, uint8_t *mapped, hipStream_t st);
+hipError_t launch_select_windows(const sw_batch &b, const uint32_t *ids, uint32_t n, sw_window *out,
+                                 hipStream_t st);
 int traceback_waves_per_block();
 hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &sc,
                                   const uint32_t *sel, const uint32_t *ids, const uint32_t *seg,

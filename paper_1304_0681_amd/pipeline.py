@@ -13,15 +13,43 @@ from __future__ import annotations
 import numpy as np
 
 from . import (SW_WANT_ENDS, DeviceBatch, aln_to_numpy, sw_batch_score, sw_batch_traceback,
-               sw_best_per_read, sw_graph_begin, sw_graph_destroy, sw_graph_end, sw_graph_launch)
+               sw_best_per_read, sw_graph_begin, sw_graph_destroy, sw_graph_end, sw_graph_launch,
+               sw_select_windows)
 
 SCORING = (5, -4, -10, -1)
 
 
+class BestBandTraceback:
+    """Traceback of each read's best window over its band.
+
+    The best window of every read (ids from sw_best_per_read) is copied into a
+    window list of its own (sw_select_windows), those windows are scored again
+    with their end cells (SW_WANT_ENDS: one pass over one window per read), and
+    the traceback's DP then covers only the columns each best alignment can
+    reach (sw_batch_traceback with the hits).  Results equal the traceback of the
+    best pairs over their whole windows; the output rows are the reads.  Fixed
+    device buffers, so a pass can be captured in a graph."""
+
+    def __init__(self, ctx, db: DeviceBatch, n_reads: int, scoring=SCORING):
+        import torch
+        self.ctx, self.scoring, self.n_reads = ctx, scoring, int(n_reads)
+        self.win = torch.empty(self.n_reads * 12, dtype=torch.uint8, device="cuda")
+        self.hits = torch.empty((self.n_reads, 3), dtype=torch.int32, device="cuda")
+        self.ids = torch.arange(self.n_reads, dtype=torch.int32, device="cuda")
+        self.view = db.view(self.win, self.n_reads)
+
+    def run(self, batch, best_pair, aln, ops, ops_stride, stream=None):
+        """`batch`: the batch (or view) best_pair indexes into."""
+        sw_select_windows(self.ctx, batch, best_pair, self.n_reads, self.win, stream)
+        sw_batch_score(self.ctx, self.view, self.scoring, SW_WANT_ENDS, self.hits, stream)
+        sw_batch_traceback(self.ctx, self.view, self.scoring, self.ids, self.n_reads, aln, ops,
+                           ops_stride, stream, hits=self.hits)
+
+
 class AlignPass:
-    """`band`: score with end cells and let the traceback's DP cover only the
-    columns each best alignment can reach (same results; pays where the reads
-    score on the int32 path, i.e. reads longer than 100 nt)."""
+    """`band`: trace back each read's best window over its band (BestBandTraceback:
+    the best windows are scored again with their end cells, then the traceback's
+    DP covers only the columns each alignment can reach); same results."""
 
     def __init__(self, ctx, db: DeviceBatch, scoring=SCORING, t_map: int = 0,
                  ops_stride: int | None = None, band: bool = False):
@@ -39,19 +67,21 @@ class AlignPass:
         self.mapped = torch.empty(n_reads, dtype=torch.uint8, device=dev)
         self.aln = torch.empty((n_reads, 7), dtype=torch.int32, device=dev)
         self.ops = torch.empty((n_reads, self.ops_stride), dtype=torch.int32, device=dev)
+        self.bbt = BestBandTraceback(ctx, db, n_reads, scoring) if self.band else None
         self.graph = None
 
     def run(self, stream=None, pack=True):
         """Encode (optional), score, best hit per read, traceback of the best hits."""
         if pack:
             self.db.pack_reads(stream)
-        sw_batch_score(self.ctx, self.db, self.scoring, SW_WANT_ENDS if self.band else 0, self.hits,
-                       stream)
+        sw_batch_score(self.ctx, self.db, self.scoring, 0, self.hits, stream)
         sw_best_per_read(self.ctx, self.db, self.hits, self.t_map, self.best_pair, self.best_score,
                          self.mapped, stream)
-        sw_batch_traceback(self.ctx, self.db, self.scoring, self.best_pair, self.db.n_reads,
-                           self.aln, self.ops, self.ops_stride, stream,
-                           hits=self.hits if self.band else None)
+        if self.bbt is not None:
+            self.bbt.run(self.db, self.best_pair, self.aln, self.ops, self.ops_stride, stream)
+        else:
+            sw_batch_traceback(self.ctx, self.db, self.scoring, self.best_pair, self.db.n_reads,
+                               self.aln, self.ops, self.ops_stride, stream)
 
     def capture(self, stream, pack=True):
         """Record run() as a graph on `stream` (a created torch.cuda.Stream).  One

@@ -17,7 +17,11 @@ compute of chunk i.  The results of chunk i - 1 are copied out once chunk i has
 passed its filter stage, so that those copies (kernels writing to host memory)
 run beside the arithmetic-bound scoring instead of the memory-bound filter
 kernels they would slow down.  The reference stays resident (packed once); host
-buffers are pinned allocations so that the copies are asynchronous.
+buffers are pinned allocations so that the copies are asynchronous.  The overlap
+needs the three streams on different hardware queues: the runtime maps streams
+onto a few queues per process (GPU_MAX_HW_QUEUES, 4 by default), and in a process
+that has created other streams before, two of these can share one, which
+serializes copies and compute (results stay the same).
 """
 from __future__ import annotations
 

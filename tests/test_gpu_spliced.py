@@ -53,11 +53,12 @@ def check(b, out, best, bp, ra, rops):
             f"seed {k}: {oracle.cigar_string(go[k, :n])} vs {oracle.cigar_string(rops[k, :n])}"
 
 
-def test_spliced_seeds_eager(ctx, spliced):
+@pytest.mark.parametrize("band", [False, True])
+def test_spliced_seeds_eager(ctx, spliced, band):
     b, ref, best, bp, ra, rops = spliced
     assert b.n_reads > 2000 and b.windows["len"].max() > 900
     db = sw.DeviceBatch.from_synth(ctx, b)
-    ap = AlignPass(ctx, db, SC)
+    ap = AlignPass(ctx, db, SC, band=band)
     ap.run()
     torch.cuda.synchronize()
     h = sw.hits_to_numpy(ap.hits)
@@ -65,18 +66,22 @@ def test_spliced_seeds_eager(ctx, spliced):
     check(b, ap.results(), best, bp, ra, rops)
 
 
-def test_spliced_seeds_graph_replays(ctx, spliced):
+@pytest.mark.parametrize("band", [False, True])
+def test_spliced_seeds_graph_replays(ctx, spliced, band):
     """The captured pass replays correctly several times, with unrelated eager
-    work and synchronisations between replays, and its outputs cleared before
-    each replay."""
+    work and synchronisations between replays, and its outputs (and, with the
+    band, the best windows and their hits) cleared before each replay."""
     b, ref, best, bp, ra, rops = spliced
     db = sw.DeviceBatch.from_synth(ctx, b)
-    ap = AlignPass(ctx, db, SC)
+    ap = AlignPass(ctx, db, SC, band=band)
     s = torch.cuda.Stream()
     ap.capture(s)
     try:
         for rep in range(3):
-            for t in (ap.hits, ap.best_pair, ap.best_score, ap.aln, ap.ops):
+            bufs = [ap.hits, ap.best_pair, ap.best_score, ap.aln, ap.ops]
+            if band:
+                bufs += [ap.bbt.win, ap.bbt.hits]
+            for t in bufs:
                 t.fill_(-3)
             junk = torch.arange(1 << 20, device="cuda", dtype=torch.float32).sum()
             torch.cuda.synchronize()
