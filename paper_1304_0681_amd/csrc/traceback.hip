@@ -19,9 +19,9 @@
 // 32-bit words (8 codes each, the lane's first row in the highest nibble used),
 // so each lane writes whole words per step and a tile needs no multiple of 8
 // rows per lane (104 rows cover 100-nt queries, 160 rows 150-nt ones).  The
-// first lane of each group then walks back from the end cell (smallest window
-// column, then smallest read row among the maxima) and run-length encodes the
-// ops.
+// lanes of each group then walk back together from the end cell (smallest window
+// column, then smallest read row among the maxima), G cells per step, and the
+// first lane run-length encodes the ops.
 #include "internal.h"
 
 namespace hpgsw {
@@ -303,171 +303,163 @@ __global__ void __launch_bounds__(64 * kWaves, RPL == 20 ? 3 : 1) k_sw_traceback
         }
         __threadfence_block();   // code stores of the whole wave before the walk
 
-        if (active && first) {
-            sw_aln a;
-            a.status = 0;
-            uint32_t *out = P.ops + (uint64_t)k_sel * P.ops_stride;
-            if (best <= 0) {
-                a.score = 0;
-                a.read_begin = a.read_end = a.ref_begin = a.ref_end = -1;
-                a.n_ops = 0;
-            } else {
-                // walk back; runs are collected last-to-first in `runs`; v is the
-                // value of the current state's matrix at (i, c)
-                int i = rbest, c = cbest, state = 0, bi = rbest, bc = cbest, v = best;
-                uint32_t nruns = 0, cur_op = 0xFFu, cur_len = 0;
-                // Most steps of the walk follow a diagonal (match runs), so a miss
-                // loads the codes of the next 8 cells of the diagonal at once
-                // (independent loads; indices clamped into the slot, and a clamped
-                // entry is never asked for) and the following steps read registers.
-                uint32_t pw[8];                              // codes, shifted down
-                int pi = -(1 << 30), pc = -(1 << 30);      // the diagonal held starts at (pi, pc)
-                auto code_at = [&](int ii, int cc) -> uint32_t {
-                    const int k = pc - cc;
-                    if (k >= 0 && k < 8 && pi - ii == k) {
-                        uint32_t cv = pw[0];
-#pragma unroll
-                        for (int q = 1; q < 8; ++q)
-                            cv = k == q ? pw[q] : cv;
-                        return cv;
+        if (active) {
+            // Walk back.  The G lanes of the group hold the same walk state and look
+            // at G cells at once along the current direction: in H state the cells
+            // of the diagonal (i - q, c - q), whose H values follow from v and the
+            // substitution scores of the cells before them (a prefix sum over the
+            // group), so a whole run of diagonal steps advances in one iteration; in
+            // a gap the extension bits of the next G cells, so a gap of any length
+            // closes in one or a few iterations.  Runs are collected last-to-first
+            // in `runs` by the first lane.
+            const int q = l;
+            const int gbase = grp * G;
+            const uint64_t gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << gbase);
+            int i = rbest, c = cbest, state = 0, bi = rbest, bc = cbest, v = best;
+            uint32_t nruns = 0, cur_op = 0xFFu, cur_len = 0;
+            const uint32_t max_runs = (uint32_t)(m + n + 2);
+            // code of an in-bounds cell: lane-layout position of its row (strip,
+            // lane, row in the lane), then its nibble in the lane's word
+            auto code_of = [&](int ii, int cc) -> uint32_t {
+                const int sp = STRIP ? (int)((uint32_t)ii / (uint32_t)SR) : 0;
+                const int rs = ii - sp * SR;
+                const int ln = (int)((uint32_t)rs / (uint32_t)RPL), r = rs - ln * RPL;
+                const uint32_t wv = slot_codes[(uint32_t)cc * col_words + (uint32_t)((sp * G + ln) * WPL + (r >> 3))];
+                const int nq = min(8, RPL - (r & ~7));   // rows in the row's word
+                return (wv >> (4u * (uint32_t)(nq - 1 - (r & 7)))) & 15u;
+            };
+            // substitution score of an in-bounds cell; positions are 32-bit offsets
+            // from the 16-base words holding the pair's first read and window bases
+            const uint32_t *rdw = P.reads + (roff >> 4);
+            const uint32_t *fww = P.ref + ((uint64_t)rb >> 4);
+            const uint32_t r0 = (uint32_t)(roff & 15), f0 = (uint32_t)((uint64_t)rb & 15);
+            auto subst_of = [&](int ii, int cc) -> int {
+                const uint32_t pos = r0 + (uint32_t)(w.strand ? m - 1 - ii : ii);
+                const uint32_t fpos = f0 + (uint32_t)cc;
+                uint32_t qb = (rdw[pos >> 4] >> (2u * (pos & 15u))) & 3u;
+                if (w.strand)
+                    qb = 3u - qb;
+                const uint32_t fb = (fww[fpos >> 4] >> (2u * (fpos & 15u))) & 3u;
+                return qb == fb ? P.ma : P.mi;
+            };
+            auto emit = [&](uint32_t op, uint32_t cnt) {
+                if (op == cur_op) {
+                    cur_len += cnt;
+                } else {
+                    if (cur_len && nruns < max_runs) {
+                        if (first)
+                            runs[nruns] = (cur_len << 4) | cur_op;
+                        ++nruns;
                     }
-                    // lane-layout position of row ii (strip, lane, row in the lane);
-                    // each further entry is one row back (clamped at row 0)
-                    int sp = STRIP ? (int)((uint32_t)ii / (uint32_t)SR) : 0;
-                    const int rs = ii - sp * SR;
-                    int ln = (int)((uint32_t)rs / (uint32_t)RPL), r = rs - ln * RPL;
-                    uint32_t sh[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const uint32_t c2 = (uint32_t)max(cc - q, 0);
-                        pw[q] = slot_codes[c2 * col_words + (uint32_t)((sp * G + ln) * WPL + (r >> 3))];
-                        const int nq = min(8, RPL - (r & ~7));   // rows in the row's word
-                        sh[q] = 4u * (uint32_t)(nq - 1 - (r & 7));
-                        const bool at0 = ((STRIP ? sp : 0) | ln | r) == 0;
-                        const bool wrap = r == 0;
-                        r = at0 ? 0 : (wrap ? RPL - 1 : r - 1);
-                        ln = at0 ? 0 : (wrap ? ln - 1 : ln);
-                        if (STRIP) {
-                            const bool wrap2 = ln < 0;
-                            ln = wrap2 ? G - 1 : ln;
-                            sp = wrap2 ? sp - 1 : sp;
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        pw[q] = (pw[q] >> sh[q]) & 15u;
-                    pi = ii;
-                    pc = cc;
-                    return pw[0];
-                };
-                // substitution score of (ii, cc).  Positions are 32-bit offsets from
-                // the 16-base word holding the pair's first read base (first window
-                // base); the walk moves back one base at a time, so it holds the
-                // current word of the read and of the window and has the next word
-                // in the walk's direction in flight (clamped to the pair's words).
-                const uint32_t *rdw = P.reads + (roff >> 4);
-                const uint32_t *fww = P.ref + ((uint64_t)rb >> 4);
-                const uint32_t r0 = (uint32_t)(roff & 15), f0 = (uint32_t)((uint64_t)rb & 15);
-                const uint32_t rd_last = (r0 + (uint32_t)m - 1) >> 4;
-                auto read_pos = [&](int ii) -> uint32_t {
-                    return r0 + (uint32_t)(w.strand ? m - 1 - ii : ii);
-                };
-                auto read_next = [&](uint32_t wi) -> uint32_t {
-                    return w.strand ? min(wi + 1, rd_last) : (wi > 0 ? wi - 1 : 0u);
-                };
-                uint32_t rw_at = read_pos(i) >> 4, fw_at = (f0 + (uint32_t)c) >> 4;
-                uint32_t rw = rdw[rw_at], fw = fww[fw_at];
-                uint32_t rn_at = read_next(rw_at), fn_at = fw_at > 0 ? fw_at - 1 : 0u;
-                uint32_t rn = rdw[rn_at], fn = fww[fn_at];
-                auto subst = [&](int ii, int cc) -> int {
-                    const uint32_t pos = read_pos(ii), fpos = f0 + (uint32_t)cc;
-                    if ((pos >> 4) != rw_at) {
-                        rw_at = pos >> 4;
-                        rw = rw_at == rn_at ? rn : rdw[rw_at];
-                        rn_at = read_next(rw_at);
-                        rn = rdw[rn_at];
-                    }
-                    if ((fpos >> 4) != fw_at) {
-                        fw_at = fpos >> 4;
-                        fw = fw_at == fn_at ? fn : fww[fw_at];
-                        fn_at = fw_at > 0 ? fw_at - 1 : 0u;
-                        fn = fww[fn_at];
-                    }
-                    uint32_t q = (rw >> (2u * (pos & 15u))) & 3u;
-                    if (w.strand)
-                        q = 3u - q;
-                    const uint32_t f = (fw >> (2u * (fpos & 15u))) & 3u;
-                    return q == f ? P.ma : P.mi;
-                };
-                const uint32_t max_runs = (uint32_t)(m + n + 2);
-                auto emit = [&](uint32_t op) {
-                    if (op == cur_op) {
-                        ++cur_len;
-                    } else {
-                        if (cur_len && nruns < max_runs)
-                            runs[nruns++] = (cur_len << 4) | cur_op;
-                        cur_op = op;
-                        cur_len = 1;
-                    }
-                };
+                    cur_op = op;
+                    cur_len = cnt;
+                }
+            };
+            if (best > 0) {
                 for (;;) {
-                    if (state == 0 && (i < 0 || c < 0 || v == 0))
-                        break;
-                    // one code per step: the cell itself (H), or the cell before it
-                    // in the gap's direction (the gap's extension bit); a gap that
-                    // reaches the matrix edge opens there
-                    const bool need = state == 0 || (state == 1 ? c > 0 : i > 0);
-                    const uint32_t code = need ? code_at(state == 2 ? i - 1 : i, state == 1 ? c - 1 : c) : 0u;
                     if (state == 0) {
-                        if (!(code & 8u)) {             // diagonal
-                            emit(SW_OP_M);
-                            v -= subst(i, c);
-                            bi = i;
-                            bc = c;
-                            --i;
-                            --c;
-                        } else {
-                            state = (code & 4u) ? 2 : 1;   // 1: deletion run, 2: insertion run
+                        if (i < 0 || c < 0 || v == 0)
+                            break;
+                        const int ii = i - q, cc = c - q;
+                        const bool inb = ii >= 0 && cc >= 0;
+                        uint32_t code = 8u;
+                        int sq = 0;
+                        if (inb) {
+                            code = code_of(ii, cc);
+                            sq = subst_of(ii, cc);
+                        }
+                        int incl = sq;   // inclusive prefix sum of the scores over the group
+#pragma unroll
+                        for (int off = 1; off < G; off <<= 1) {
+                            const int t = __shfl_up(incl, off, G);
+                            if (q >= off)
+                                incl += t;
+                        }
+                        // this cell continues the diagonal run when it is inside the
+                        // matrix, its H (v minus the scores of the cells before it)
+                        // is not 0 and its H comes from the diagonal
+                        const bool ok = inb && v - (incl - sq) != 0 && !(code & 8u);
+                        const uint64_t bad = __ballot(!ok) & gmask;
+                        const int r = bad ? (int)__builtin_ctzll(bad) - gbase : G;
+                        if (r > 0) {
+                            emit(SW_OP_M, (uint32_t)r);
+                            v -= __shfl(incl, gbase + r - 1);
+                            bi = i - (r - 1);
+                            bc = c - (r - 1);
+                            i -= r;
+                            c -= r;
+                        }
+                        if (r < G) {
+                            // the cell that ended the run is (i, c) now: a stop (the
+                            // loop's test) or the start of a gap
+                            const uint32_t code_r = __shfl(code, gbase + r);
+                            if (i >= 0 && c >= 0 && v != 0)
+                                state = (code_r & 4u) ? 2 : 1;   // 1: deletion run, 2: insertion run
                         }
                     } else {
-                        const uint32_t ext = state == 1 ? (code >> 1) & 1u : code & 1u;
-                        emit(state == 1 ? SW_OP_D : SW_OP_I);
+                        // extension bits of the cells before (i, c) in the gap's
+                        // direction; a gap reaching the matrix edge opens there
+                        const int ii = state == 2 ? i - 1 - q : i;
+                        const int cc = state == 1 ? c - 1 - q : c;
+                        bool ext = false;
+                        if (ii >= 0 && cc >= 0) {
+                            const uint32_t code = code_of(ii, cc);
+                            ext = state == 1 ? (code & 2u) != 0 : (code & 1u) != 0;
+                        }
+                        const uint64_t opens = __ballot(!ext) & gmask;
+                        const int e = opens ? (int)__builtin_ctzll(opens) - gbase : G;
+                        const int steps = e < G ? e + 1 : G;   // e extensions, then the opening
+                        emit(state == 1 ? SW_OP_D : SW_OP_I, (uint32_t)steps);
                         if (state == 1)
-                            --c;
+                            c -= steps;
                         else
-                            --i;
-                        v -= ext ? ge : go;
-                        if (!ext)
+                            i -= steps;
+                        v -= e * ge + (e < G ? go : 0);
+                        if (e < G)
                             state = 0;
                     }
                 }
-                if (cur_len && nruns < max_runs)
-                    runs[nruns++] = (cur_len << 4) | cur_op;
-                a.score = best;
-                a.read_begin = bi;
-                a.read_end = rbest;
-                a.ref_begin = bc + c_lo;
-                a.ref_end = cbest + c_lo;
-                uint32_t k = 0;
-                bool trunc = false;
-                auto put = [&](uint32_t v) {
-                    if (k < P.ops_stride)
-                        out[k] = v;
-                    else
-                        trunc = true;
-                    ++k;
-                };
-                if (bi > 0)
-                    put(((uint32_t)bi << 4) | SW_OP_S);
-                for (int q = (int)nruns - 1; q >= 0; --q)
-                    put(runs[q]);
-                if (m - 1 - rbest > 0)
-                    put(((uint32_t)(m - 1 - rbest) << 4) | SW_OP_S);
-                a.n_ops = trunc ? P.ops_stride : k;
-                if (trunc)
-                    a.status |= 1u;
+                if (cur_len && nruns < max_runs) {
+                    if (first)
+                        runs[nruns] = (cur_len << 4) | cur_op;
+                    ++nruns;
+                }
             }
-            P.aln[k_sel] = a;
+            if (first) {
+                sw_aln a;
+                a.status = 0;
+                uint32_t *out = P.ops + (uint64_t)k_sel * P.ops_stride;
+                if (best <= 0) {
+                    a.score = 0;
+                    a.read_begin = a.read_end = a.ref_begin = a.ref_end = -1;
+                    a.n_ops = 0;
+                } else {
+                    a.score = best;
+                    a.read_begin = bi;
+                    a.read_end = rbest;
+                    a.ref_begin = bc + c_lo;
+                    a.ref_end = cbest + c_lo;
+                    uint32_t k = 0;
+                    bool trunc = false;
+                    auto put = [&](uint32_t val) {
+                        if (k < P.ops_stride)
+                            out[k] = val;
+                        else
+                            trunc = true;
+                        ++k;
+                    };
+                    if (bi > 0)
+                        put(((uint32_t)bi << 4) | SW_OP_S);
+                    for (int qq = (int)nruns - 1; qq >= 0; --qq)
+                        put(runs[qq]);
+                    if (m - 1 - rbest > 0)
+                        put(((uint32_t)(m - 1 - rbest) << 4) | SW_OP_S);
+                    a.n_ops = trunc ? P.ops_stride : k;
+                    if (trunc)
+                        a.status |= 1u;
+                }
+                P.aln[k_sel] = a;
+            }
         }
         __threadfence_block();   // the walk's reads finish before the slot is reused
     }
