@@ -513,6 +513,15 @@ def bench_stream(ctx, args):
                                           p_ca.best_score.cpu().numpy(),
                                           b_ca.windows["read_id"].astype(np.int64), t_map,
                                           target=0.9995)
+    tune = None
+    if not args.no_autotune:
+        # tiles and workgroups per CU for the mates' query-length class, tuned on
+        # the calibration mates in the mode the stream scores its kept pairs in
+        tune = [t for t in sw.sw_autotune(ctx, db_ca, SCORING, sw.SW_WANT_ENDS, repeats=3)
+                if t["path"]]
+        log("stream autotune: " + "; ".join(
+            f"m<={t['m_max']}: {t['G']}x{t['RPL']} bpc {t['blocks_per_cu']} {t['ms']:.2f} ms "
+            f"(default {t['ms_default']:.2f})" for t in tune))
     del f_ca, p_ca, db_ca, b_ca
     # two distinct chunks, generated once and cycled (the generator is far slower
     # than the GPU); plain SW on each gives the recall reference
@@ -582,6 +591,10 @@ def bench_stream(ctx, args):
         "includes": "host->device copies of reads and windows, encode, features, MLP, decision, "
                     "compaction, SW on kept pairs, best hit, traceback, device->host copies",
         "setup_seconds": round(time.perf_counter() - t0 - wall, 1),
+        "autotune": None if tune is None else [
+            {"m_max": t["m_max"], "tile": [t["G"], t["RPL"]], "blocks_per_cu": t["blocks_per_cu"],
+             "path": PATHS.get(t["path"], "int32"), "ms": round(t["ms"], 3),
+             "ms_default": round(t["ms_default"], 3)} for t in tune],
     }
 
 
