@@ -21,7 +21,10 @@
 // rows per lane (104 rows cover 100-nt queries, 160 rows 150-nt ones).  The
 // lanes of each group then walk back together from the end cell (smallest window
 // column, then smallest read row among the maxima), G cells per step, and the
-// first lane run-length encodes the ops.
+// first lane run-length encodes the ops.  Given the score pass's hits (score
+// and end cell), a pair's DP covers only the window columns an alignment of
+// that score ending there can reach (tb_band), which changes no code the walk
+// reads.
 #include "internal.h"
 
 namespace hpgsw {
