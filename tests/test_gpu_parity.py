@@ -163,6 +163,49 @@ def test_traceback_band_from_score_ends(ctx, sc):
     assert_aln_equal(a, o, ref, rops)
 
 
+def test_select_windows(ctx):
+    """sw_select_windows copies the windows of the given pair ids; ids at or past
+    the batch's pairs (also past a device-side pair count) give a window with an
+    invalid read id, which the score and traceback calls answer as invalid."""
+    b = synth.config1(seed=synth.BASE_SEED + 63, n_reads=40)
+    db = sw.DeviceBatch.from_synth(ctx, b)
+    ids = np.array([3, 0, 39, b.n_pairs, 0xFFFFFFFF, 7], dtype=np.uint32)
+    d_ids = torch.from_numpy(ids.view(np.int32)).cuda()
+    out = torch.full((len(ids) * 12,), 0x5A, dtype=torch.uint8, device="cuda")
+    sw.sw_select_windows(ctx, db, d_ids, len(ids), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(b.windows.dtype)
+    for k, p in enumerate(ids):
+        if p < b.n_pairs:
+            assert got[k].tobytes() == b.windows[p].tobytes()
+        else:
+            assert got[k]["read_id"] == 0xFFFFFFFF and got[k]["len"] == 0
+    # a count on the device limits the valid ids to those below it
+    cnt = torch.tensor([5], dtype=torch.int32, device="cuda")
+    sw.sw_select_windows(ctx, db.view(db.win, b.n_pairs, cnt), d_ids, len(ids), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(b.windows.dtype)
+    for k, p in enumerate(ids):
+        if p < 5:
+            assert got[k].tobytes() == b.windows[p].tobytes()
+        else:
+            assert got[k]["read_id"] == 0xFFFFFFFF
+    # the gathered list scores like the original pairs and marks the invalid ones
+    view = db.view(out, len(ids))
+    sw.sw_select_windows(ctx, db, d_ids, len(ids), out)
+    hits = torch.full((len(ids), 3), -7, dtype=torch.int32, device="cuda")
+    sw.sw_batch_score(ctx, view, SC, sw.SW_WANT_ENDS, hits)
+    torch.cuda.synchronize()
+    h = sw.hits_to_numpy(hits)
+    ref, _ = oracle.align_batch(b, SC, mode=0)
+    for k, p in enumerate(ids):
+        if p < b.n_pairs:
+            for f in ("score", "read_end", "ref_end"):
+                assert h[k][f] == ref[p][f]
+        else:
+            assert h[k]["score"] == -1
+
+
 def test_traceback_band_paired_mates(ctx):
     """150-nt mates against 16 windows of 200-1,000 nt (the stream's shape): best
     window per mate traced with and without the band, both equal to the oracle."""
