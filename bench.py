@@ -383,6 +383,8 @@ def bench_spliced(ctx, args):
     t_step = (time.perf_counter() - t1) / args.steps
     bp = ap.best_pair.cpu().numpy().view(np.uint32)
     aln = sw.aln_to_numpy(ap.aln)
+    # the filtered form grows context scratch, which a live graph forbids
+    ap.close()
     filtered = None if args.no_filter else _spliced_filtered(ctx, args, b, db, ap, t_step)
     ok = bp < b.n_pairs
     m = b.read_len[b.windows["read_id"][bp[ok]]].astype(np.int64)

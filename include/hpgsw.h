@@ -136,7 +136,13 @@ const char *sw_last_error(const sw_ctx *ctx);
  * encoded as A and counted into *d_bad (device uint32, may be NULL; it is
  * incremented, not cleared).  The read and reference encoding of Sec. 2,
  * stage A (reads are held with their sequence), in the 2-bit form the
- * aligner reads. */
+ * aligner reads.
+ * Invalid input is reported through *d_bad, not through the return value: the
+ * call is asynchronous, so the count is known only once the stream has
+ * synchronised.  A nonzero count means d_out is not the input sequence, and
+ * every result computed from it is invalid: the caller must clear the counter
+ * before the call and check it afterwards (pass d_bad whenever the input may
+ * hold other bytes, e.g. the N of a sequencer). */
 sw_status sw_pack2b(sw_ctx *ctx, const uint8_t *d_ascii, uint64_t n, uint32_t *d_out,
                     uint32_t *d_bad, void *stream);
 
@@ -193,7 +199,13 @@ sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *batch, const sw_scorin
  * SW_E_STATE: make the same calls once, uncaptured, before capturing.  The
  * stream must be a created stream (not the null stream); phase timing must be
  * off.  If a captured call fails, end the capture with sw_graph_end (which
- * then returns an error too) before using the context again. */
+ * then returns an error too) before using the context again.
+ * A graph's kernels use the context's scratch buffers as they were at capture
+ * time.  While any graph ended on a context is alive (until sw_graph_destroy),
+ * a call on that context that would have to grow a scratch buffer (a larger
+ * batch, a larger SW_OPT_TB_SCRATCH_MB) fails with SW_E_STATE and changes
+ * nothing; destroy the graphs first.  sw_autotune, sw_mlp_grad and
+ * sw_mlp_train_step cannot be captured (SW_E_STATE). */
 typedef struct sw_graph sw_graph;
 sw_status sw_graph_begin(sw_ctx *ctx, void *stream);
 sw_status sw_graph_end(sw_ctx *ctx, void *stream, sw_graph **out);

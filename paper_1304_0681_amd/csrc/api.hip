@@ -45,6 +45,9 @@ struct sw_ctx {
     size_t tb_budget = 2ull << 30;
     // inside sw_graph_begin / sw_graph_end: no allocation, no host synchronisation
     bool capturing = false;
+    // graphs ended on this context and not yet destroyed: their kernel nodes hold
+    // the current scratch pointers, so no scratch buffer may be freed or moved
+    int live_graphs = 0;
     // filter scratch: read segments (first, last, count) and compaction offsets
     uint32_t *seg = nullptr;
     size_t seg_bytes = 0;
@@ -121,13 +124,21 @@ sw_status check_batch(sw_ctx *ctx, const sw_batch *b)
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-sw_status ensure(sw_ctx *ctx, void **buf, size_t *have, size_t need)
+// Grow a scratch buffer to at least `need` bytes.  `graph_visible`: the buffer
+// may be referenced by a captured graph (every context scratch except the MLP
+// training workspace, whose calls cannot be captured), so it may not move while
+// such a graph is alive.
+sw_status ensure(sw_ctx *ctx, void **buf, size_t *have, size_t need, bool graph_visible = true)
 {
     if (*have >= need)
         return SW_OK;
     if (ctx->capturing)
         return fail(ctx, SW_E_STATE, "scratch of %zu bytes needed during graph capture: make the "
                     "same calls once before capturing", need);
+    if (graph_visible && ctx->live_graphs > 0)
+        return fail(ctx, SW_E_STATE, "scratch of %zu bytes needed while %d captured graph(s) of this "
+                    "context still use the current scratch: destroy them first", need,
+                    ctx->live_graphs);
     const size_t old = *have;
     if (*buf)
         HIP_TRY(ctx, hipFree(*buf));
@@ -139,15 +150,18 @@ sw_status ensure(sw_ctx *ctx, void **buf, size_t *have, size_t need)
     return SW_OK;
 }
 
-sw_status bucket_scratch(sw_ctx *ctx, uint32_t n_items, BucketScratch *s)
+// Bytes of the bucketing scratch for n_items pairs (layout of carve_bucket).
+constexpr size_t bucket_bytes(size_t n_items)
+{
+    return ((4 * (n_items ? n_items : 1) + 255) & ~size_t(255)) * 2 +
+           ((4 * kNumBins + 255) & ~size_t(255)) + 3 * ((4 * 2 * kNumClasses + 255) & ~size_t(255));
+}
+
+// Lay the bucketing scratch of n_items pairs out from `base` (bucket_bytes long).
+void carve_bucket(void *base, uint32_t n_items, BucketScratch *s)
 {
     const size_t n = std::max<uint32_t>(n_items, 1);
-    const size_t need = align_up(4 * n) * 2 + align_up(4 * kNumBins) + align_up(4 * 2 * kNumClasses) +
-                        align_up(4 * kNumClasses) + align_up(4 * 2 * kNumClasses);
-    sw_status st = ensure(ctx, &ctx->bscratch, &ctx->bscratch_bytes, need);
-    if (st)
-        return st;
-    char *p = static_cast<char *>(ctx->bscratch);
+    char *p = static_cast<char *>(base);
     s->bin = reinterpret_cast<uint32_t *>(p);
     p += align_up(4 * n);
     s->ids = reinterpret_cast<uint32_t *>(p);
@@ -159,8 +173,17 @@ sw_status bucket_scratch(sw_ctx *ctx, uint32_t n_items, BucketScratch *s)
     s->counter = reinterpret_cast<uint32_t *>(p);
     p += align_up(4 * kNumClasses);
     s->maxlen = reinterpret_cast<uint32_t *>(p);
+}
+
+sw_status bucket_scratch(sw_ctx *ctx, uint32_t n_items, BucketScratch *s)
+{
+    sw_status st = ensure(ctx, &ctx->bscratch, &ctx->bscratch_bytes, bucket_bytes(n_items));
+    if (st)
+        return st;
+    carve_bucket(ctx->bscratch, n_items, s);
     return SW_OK;
 }
+
 
 }  // namespace
 
@@ -236,9 +259,15 @@ sw_status sw_pack2b(sw_ctx *ctx, const uint8_t *d_ascii, uint64_t n, uint32_t *d
     return SW_OK;
 }
 
-sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint32_t flags,
-                         sw_hit *d_hits, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Arguments of a score call; SW_OK when the call has work to do (*work set).
+sw_status check_score_call(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint32_t flags,
+                           sw_hit *d_hits, bool *work)
 {
+    *work = false;
     if (!ctx)
         return fail(nullptr, SW_E_INVALID, "ctx is NULL");
     sw_status st = check_batch(ctx, b);
@@ -252,21 +281,24 @@ sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
         return SW_OK;
     if (!d_hits)
         return fail(ctx, SW_E_INVALID, "d_hits is NULL");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    HIP_TRY(ctx, hipSetDevice(ctx->device));
-    BucketScratch bs;
-    if ((st = bucket_scratch(ctx, b->n_pairs, &bs)))
-        return st;
-    // strip buffers only when some read may exceed the largest single-strip class
-    const bool may_strip = b->reads_len > (uint64_t)kDefaultClasses[kNumClasses - 2].m_max;
-    if (may_strip && !ctx->strip_buf) {
-        if (ctx->capturing)
-            return fail(ctx, SW_E_STATE, "strip buffers needed during graph capture: make the same "
-                        "calls once before capturing");
-        ctx->strip_waves = 64;
-        HIP_TRY(ctx, hipMalloc(reinterpret_cast<void **>(&ctx->strip_buf),
-                               sizeof(int2) * 65536ull * (size_t)ctx->strip_waves));
-    }
+    *work = true;
+    return SW_OK;
+}
+
+// Some read of the batch may exceed the largest single-strip class.
+bool batch_may_strip(const sw_batch *b)
+{
+    return b->reads_len > (uint64_t)kDefaultClasses[kNumClasses - 2].m_max;
+}
+
+// Bucketing and the class kernels of one score call, on scratch the caller
+// provides (strip rows for `strip_waves` waves of 65,536 entries each when the
+// batch may hold strip-class reads).
+sw_status score_dispatch(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint32_t flags,
+                         sw_hit *d_hits, hipStream_t s, const BucketScratch &bs, int2 *strip_buf,
+                         int strip_waves)
+{
+    const bool may_strip = batch_may_strip(b);
     if (ctx->timing)
         HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
     HIP_TRY(ctx, launch_bucket(*b, nullptr, b->n_pairs, bs, d_hits, nullptr, s));
@@ -289,7 +321,7 @@ sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
     p.go = sc->gap_open;
     p.ge = sc->gap_extend;
     p.hits = d_hits;
-    p.strip_buf = ctx->strip_buf;
+    p.strip_buf = strip_buf;
     p.strip_stride = 65536;
     const bool ends = flags & SW_WANT_ENDS;
     for (int c = 0; c < kNumClasses; ++c) {
@@ -306,7 +338,7 @@ sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
         const bool wide = (int64_t)sc->match * kDefaultClasses[c].m_max >= 32768;
         const int mode = ends ? (wide ? 2 : 1) : 0;
         const int wpb = score_waves_per_block();
-        const int grid = strip ? ctx->strip_waves / wpb : ctx->n_cu * ctx->blocks_per_cu[c];
+        const int grid = strip ? strip_waves / wpb : ctx->n_cu * ctx->blocks_per_cu[c];
         // packed int16 when every score of the class fits 16 bits exactly.  Only
         // the shapes in kPackedVerified run packed: a call that used the packed
         // kernel for all classes did not return, and its cause is not known.
@@ -324,6 +356,34 @@ sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
     ctx->timed_call = ctx->timing;
     return SW_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint32_t flags,
+                         sw_hit *d_hits, void *stream)
+{
+    bool work = false;
+    sw_status st = check_score_call(ctx, b, sc, flags, d_hits, &work);
+    if (st || !work)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    BucketScratch bs;
+    if ((st = bucket_scratch(ctx, b->n_pairs, &bs)))
+        return st;
+    if (batch_may_strip(b) && !ctx->strip_buf) {
+        if (ctx->capturing || ctx->live_graphs > 0)
+            return fail(ctx, SW_E_STATE, "strip buffers needed during graph capture or while a "
+                        "captured graph is alive: make the same calls once before capturing");
+        ctx->strip_waves = 64;
+        HIP_TRY(ctx, hipMalloc(reinterpret_cast<void **>(&ctx->strip_buf),
+                               sizeof(int2) * 65536ull * (size_t)ctx->strip_waves));
+    }
+    return score_dispatch(ctx, b, sc, flags, d_hits, s, bs, ctx->strip_buf, ctx->strip_waves);
+}
+
 
 sw_status sw_best_per_read(sw_ctx *ctx, const sw_batch *b, const sw_hit *d_hits, int32_t t_map,
                            uint32_t *d_best_pair, int32_t *d_best_score, uint8_t *d_mapped,
@@ -390,17 +450,18 @@ sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *b, const sw_scoring *s
     BucketScratch bs;
     if ((st = bucket_scratch(ctx, n_sel, &bs)))
         return st;
-    const TbBand band{d_hits, sc->match, -sc->gap_open, -sc->gap_extend};
-    HIP_TRY(ctx, launch_bucket(*b, d_pair_ids, n_sel, bs, nullptr, d_aln, s, band));
     // Code slots come from a fixed scratch budget; every class kernel sizes its
     // slots from the class maxima on the device and runs the waves that fit, so
-    // the call needs no host round trip and can be captured in a graph.
+    // the call needs no host round trip and can be captured in a graph.  Sized
+    // before the first launch, so that a refused call changes nothing.
     void *buf = ctx->tb;
     size_t have = ctx->tb_bytes;
     if ((st = ensure(ctx, &buf, &have, ctx->tb_budget)))
         return st;
     ctx->tb = static_cast<uint32_t *>(buf);
     ctx->tb_bytes = have;
+    const TbBand band{d_hits, sc->match, -sc->gap_open, -sc->gap_extend};
+    HIP_TRY(ctx, launch_bucket(*b, d_pair_ids, n_sel, bs, nullptr, d_aln, s, band));
     const int wpb = traceback_waves_per_block();
     const int grid = std::max(1, ctx->n_cu * 16 / wpb);
     for (int c = 0; c < kNumClasses; ++c) {
@@ -447,6 +508,7 @@ sw_status sw_graph_end(sw_ctx *ctx, void *stream, sw_graph **out)
         return fail(ctx, SW_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
     *out = new sw_graph{g, x};
+    ctx->live_graphs += 1;
     return SW_OK;
 }
 
@@ -469,6 +531,8 @@ sw_status sw_graph_destroy(sw_ctx *ctx, sw_graph *g)
     hipError_t e = hipGraphExecDestroy(g->exec);
     const hipError_t e2 = hipGraphDestroy(g->graph);
     delete g;
+    if (ctx->live_graphs > 0)
+        ctx->live_graphs -= 1;
     if (e == hipSuccess)
         e = e2;
     if (e != hipSuccess)
@@ -580,11 +644,16 @@ sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint
     memcpy(keep_bpc, ctx->blocks_per_cu, sizeof keep_bpc);
     const bool was_timing = ctx->timing;
     void *hits = nullptr;
+    bool chosen = false;   // set once the tuned shapes are in ctx; every earlier exit restores
     auto restore = [&]() {
         if (hits)
             (void)hipFree(hits);
         ctx->timing = was_timing;
         ctx->timed_call = false;
+        if (!chosen) {
+            memcpy(ctx->shapes, keep_shapes, sizeof keep_shapes);
+            memcpy(ctx->blocks_per_cu, keep_bpc, sizeof keep_bpc);
+        }
     };
     if (b->n_pairs) {
         const hipError_t e = hipMalloc(&hits, sizeof(sw_hit) * (size_t)b->n_pairs);
@@ -625,8 +694,6 @@ sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint
             sw_timing t;
             if ((st = sw_batch_score(ctx, b, sc, flags, static_cast<sw_hit *>(hits), stream)) ||
                 (st = sw_timing_get(ctx, &t))) {
-                memcpy(ctx->shapes, keep_shapes, sizeof keep_shapes);
-                memcpy(ctx->blocks_per_cu, keep_bpc, sizeof keep_bpc);
                 restore();
                 return st;
             }
@@ -685,8 +752,11 @@ sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint
             out[c].ms_default = pth ? def_ms[c] : 0.f;
         }
     }
-    HIP_TRY(ctx, hipStreamSynchronize(s));
+    chosen = true;
+    const hipError_t e = hipStreamSynchronize(s);
     restore();
+    if (e != hipSuccess)
+        return fail(ctx, SW_E_DEVICE, "sw_autotune: %s", hipGetErrorString(e));
     return SW_OK;
 }
 
@@ -716,7 +786,7 @@ namespace {
 
 sw_status mlp_workspace(sw_ctx *ctx, sw_mlp *mlp, uint32_t n)
 {
-    return ensure(ctx, &mlp->ws, &mlp->ws_bytes, mlp_workspace_bytes(n));
+    return ensure(ctx, &mlp->ws, &mlp->ws_bytes, mlp_workspace_bytes(n), false);
 }
 
 sw_status filter_scratch(sw_ctx *ctx, uint32_t n_reads, uint32_t n_pairs, uint32_t **first,
@@ -857,6 +927,8 @@ sw_status sw_mlp_grad(sw_ctx *ctx, const sw_mlp *mlp, const uint16_t *d_x, const
         return fail(ctx, SW_E_INVALID, "NULL argument");
     if (n == 0 || n > (1u << 20))
         return fail(ctx, SW_E_RANGE, "minibatch must hold 1..2^20 rows");
+    if (ctx->capturing)
+        return fail(ctx, SW_E_STATE, "sw_mlp_grad cannot be captured");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     sw_mlp *mm = const_cast<sw_mlp *>(mlp);
     sw_status st = mlp_workspace(ctx, mm, n);
@@ -876,6 +948,10 @@ sw_status sw_mlp_train_step(sw_ctx *ctx, sw_mlp *mlp, const uint16_t *d_x, const
         return fail(ctx, SW_E_RANGE, "minibatch must hold 1..2^20 rows");
     if (!(lr > 0.f))
         return fail(ctx, SW_E_INVALID, "learning rate must be positive");
+    // the step count enters Adam's bias correction on the host: a replayed graph
+    // would repeat one step's correction
+    if (ctx->capturing)
+        return fail(ctx, SW_E_STATE, "sw_mlp_train_step cannot be captured");
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     sw_status st = mlp_workspace(ctx, mlp, n);

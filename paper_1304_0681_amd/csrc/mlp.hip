@@ -566,6 +566,13 @@ __global__ void __launch_bounds__(256) k_compact(uint32_t n, const uint8_t *keep
     }
 }
 
+// Columns [B, ldt) of row blockIdx.x of a transposed operand (the K padding).
+__global__ void __launch_bounds__(64) k_zero_pad(uint16_t *T, uint32_t B, uint32_t ldt)
+{
+    for (uint32_t c = B + threadIdx.x; c < ldt; c += 64)
+        T[(uint64_t)blockIdx.x * ldt + c] = 0;
+}
+
 unsigned blocks_for(uint64_t n)
 {
     const uint64_t b = (n + 255) / 256;
@@ -629,12 +636,12 @@ hipError_t mlp_backprop(const MlpDev &W, const uint16_t *X, const float *y, uint
     float *dz = (float *)take(4ull * B);
     float *terms = (float *)take(4ull * B);
     float *GW = (float *)take(4ull * kHidden * kHidden);
-    // zero the K padding of the transposed operands
+    // zero the K padding of the transposed operands (a kernel, not memset nodes)
     hipError_t e;
     if (ldt != B) {
         for (uint16_t *q : {A1T, A2T, DZ2T, DZ1T})
-            if ((e = hipMemsetAsync(q, 0, 2ull * kHidden * ldt, st)) != hipSuccess) return e;
-        if ((e = hipMemsetAsync(XT, 0, 2ull * kIn * ldt, st)) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_zero_pad, dim3(kHidden), dim3(64), 0, st, q, B, ldt);
+        hipLaunchKernelGGL(k_zero_pad, dim3(kIn), dim3(64), 0, st, XT, B, ldt);
     }
     const uint64_t bh = (uint64_t)B * kHidden;
     // forward
