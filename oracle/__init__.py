@@ -12,9 +12,13 @@ Contents
 * ``brute.py``  enumeration of every local alignment on tiny inputs.
 * ``mlp_ref.py`` float64/float32 reference of the candidate-filter MLP.
 * ``features_ref.py`` reference of the per-candidate seed-hit features.
+* ``filter_ref.py`` reference of the filter's per-read decision and compaction.
 
 Parity status: the score, end cell, begin cell and CIGAR are pinned by brute
-force, closed forms, hand-worked examples and invariants (tests/test_oracle_*).
+force, closed forms, hand-worked examples and invariants (tests/test_oracle_*);
+the features by brute-force hit enumeration and hand-computed planted hits;
+the MLP by float64 finite differences, Adam by hand-computed steps and a
+closed form; the filter decision by hand-built cases.
 """
 from __future__ import annotations
 

@@ -75,3 +75,22 @@ def test_output_calibration_meets_target():
     lo_s, hi_s, _ = tr.calibrate(z, scores, best, rid, target=0.999)
     keep_s, _, _ = tr.filter_outcome(z, scores, best, rid, lo_s, hi_s)
     assert keep.sum() < 0.5 * keep_s.sum()
+
+
+def test_calibration_rule_equals_reference_decision():
+    """The rule the calibration evaluates (train.filter_outcome, host logic of
+    the product) keeps exactly the pairs the reference decision keeps, on
+    random logits with contiguous reads of 1-16 candidates."""
+    from oracle import filter_ref as flt
+    g = np.random.default_rng(11)
+    counts = g.integers(1, 17, 500)
+    rid = np.repeat(np.arange(len(counts)), counts)
+    z = g.normal(0, 2, len(rid)).astype(np.float32)
+    scores = g.integers(0, 100, len(rid))
+    best = np.zeros(len(counts), np.int64)
+    np.maximum.at(best, rid, scores)
+    for lo, hi, drop in ((0.0, 1.0, float("-inf")), (0.5, 0.5, -1.0), (-1.0, 2.5, -3.0)):
+        keep, _, unsure = tr.filter_outcome(z, scores, best, rid, lo, hi, drop)
+        exp_keep, n_unsure = flt.decide(z, rid, len(counts), lo, hi, drop)
+        assert (keep == exp_keep).all()
+        assert int(unsure.sum()) == n_unsure

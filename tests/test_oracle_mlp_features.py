@@ -70,6 +70,41 @@ def test_adam_first_step_is_signed_lr():
     assert t[3] == 0.0
 
 
+def test_adam_three_steps_hand_computed():
+    """Moments, bias correction and parameter after each of three steps with
+    gradients 1, -2, 0.5 (lr 0.1, beta1 0.9, beta2 0.999, eps 1e-8), worked out
+    by hand:
+      t=1: m = 0.1,    v = 0.001,     m/(1-0.9) = 1, v/(1-0.999) = 1, theta = -0.1
+      t=2: m = -0.11,  v = 0.004999,  m/0.19 = -0.5789474, v/0.001999 = 2.5007504,
+           theta = -0.1 + 0.1 * 0.5789474 / 1.5813761 = -0.0633896
+      t=3: m = -0.049, v = 0.005244001, m/0.271 = -0.1808118,
+           v/0.002997001 = 1.7497494, theta = -0.0633896 + 0.0136691 = -0.0497206"""
+    th = np.zeros(1, np.float32)
+    m = np.zeros(1, np.float32)
+    v = np.zeros(1, np.float32)
+    exp = [(0.1, 0.001, -0.1), (-0.11, 0.004999, -0.0633896465),
+           (-0.049, 0.005244001, -0.0497205803)]
+    for t, (g, (em, ev, eth)) in enumerate(zip([1.0, -2.0, 0.5], exp), start=1):
+        th, m, v = mr.adam(th, m, v, np.array([g], np.float32), t, 0.1)
+        assert abs(float(m[0]) - em) <= 1e-7 * max(1, abs(em)), (t, m)
+        assert abs(float(v[0]) - ev) <= 1e-6 * ev, (t, v)
+        assert abs(float(th[0]) - eth) <= 2e-7, (t, th)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With a constant gradient the bias-corrected moments are g and g^2 at
+    every step, so each step moves every parameter by lr against the sign of
+    its gradient: theta_t = -t * lr * sign(g).  A wrong moment decay or a bias
+    correction that does not follow the step count breaks this from step 2."""
+    g = np.array([0.3, -2.0, 1e-3, 7.0], np.float32)
+    th = np.zeros(4, np.float32)
+    m = np.zeros(4, np.float32)
+    v = np.zeros(4, np.float32)
+    for t in range(1, 8):
+        th, m, v = mr.adam(th, m, v, g, t, 0.01)
+        assert np.allclose(th, -t * 0.01 * np.sign(g), rtol=0, atol=2e-6 * t), (t, th)
+
+
 def test_training_reduces_loss():
     g = np.random.default_rng(2)
     X = g.normal(0, 1, (512, 64)).astype(np.float32)
@@ -137,3 +172,101 @@ def test_strand_symmetry():
     keep = [i for i in range(64) if i != 47]
     assert (f1[:, keep] == f0[:, keep]).all()
     assert f1[0, 3] > 0.9 and f1[1, 3] < 0.1
+
+
+def _planted_pair(seed):
+    """A read of 100 bases holding four 12-mers copied from a 300-base window at
+    (read position p, window position j) = (0, 10), (20, 150), (44, 288),
+    (88, 200), the rest random; the brute-force hit list must be exactly those."""
+    g = np.random.default_rng(seed)
+    t = g.integers(0, 4, 300).astype(np.uint8)
+    q = g.integers(0, 4, 100).astype(np.uint8)
+    for p, j in ((0, 10), (20, 150), (44, 288), (88, 200)):
+        q[p:p + 12] = t[j:j + 12]
+    return q, t
+
+
+def test_planted_hit_histograms_and_diagonals():
+    """Histograms of planted hits, worked out by hand.  P = 100 - 11 = 89 read
+    positions, J = 300 - 11 = 289 window positions.
+      read bins (16 p) // 89:   0 -> 0, 20 -> 3, 44 -> 7, 88 -> 15
+      window bins (16 j) // 289: 10 -> 0, 150 -> 8, 288 -> 15, 200 -> 11
+      diagonal bins (j - p + 100) >> 4: 110 -> 6, 230 -> 14, 344 -> 21, 212 -> 13
+    so 4 hits, 4 distinct read positions, 4 diagonal bins, the modal bin is 6
+    (all bins hold one hit; the smallest wins) with nmode = nmode3 = 1, and
+    f5 = (16 * 6 + 8 - 100) / 300.  Binning by m or n instead of P or J moves
+    p = 20 to bin 3 (still), p = 88 to bin 14 and j = 200 to bin 10."""
+    for seed in range(40):
+        q, t = _planted_pair(seed)
+        if sorted(_brute_hits(q, t)) == [(0, 10), (20, 150), (44, 288), (88, 200)]:
+            break
+    else:
+        raise AssertionError("no seed without chance hits")
+    st = fr.candidate_stats(q, t)
+    f = fr.read_features([st], [0])[0]
+    f32 = np.float32
+    one = fr.bf16_round(f32(1) / f32(89))
+    four = fr.bf16_round(f32(4) / f32(89))
+    hp = np.zeros(16, np.float32)
+    hp[[0, 3, 7, 15]] = one
+    hj = np.zeros(16, np.float32)
+    hj[[0, 8, 11, 15]] = one
+    assert (f[7:23] == hp).all(), f[7:23]
+    assert (f[23:39] == hj).all(), f[23:39]
+    assert f[0] == four and f[1] == four and f[2] == one and f[3] == one
+    assert f[4] == fr.bf16_round(f32(4) / f32(16)) and f[6] == 1.0
+    assert f[5] == fr.bf16_round(f32(16 * 6 + 8 - 100) / f32(300))
+    assert st["mode"] == 6 and st["nbins"] == 4
+
+
+def test_per_read_features_hand_computed():
+    """Three candidates of one read: A (the four planted hits above), B (the
+    whole read copied at offset 37 of a 187-base window: 89 hits on one
+    diagonal), C (a 240-base periodic window GGCA..., no hits, strand 1).
+      nmode3 = [1, 89, 0], distinct read positions = [4, 89, 0], so
+      f39 = (nmode3 - 89) / 89, f40 = (ndp - 89) / 89, f41 = [0, 1, 0],
+      f42 = [1/3, 0, 2/3], f43 = (89 - 1) / 89, f44 = 3/16,
+      f45 = n / 1000 = [0.3, 0.187, 0.24], f46 = 0.1, f47 = [0, 0, 1],
+      f48(C) = 180 / 240 G+C (two G and one C in every four bases)."""
+    for seed in range(40):
+        q, tA = _planted_pair(seed)
+        if sorted(_brute_hits(q, tA)) == [(0, 10), (20, 150), (44, 288), (88, 200)]:
+            break
+    g = np.random.default_rng(99)
+    tB = np.concatenate([g.integers(0, 4, 37), q, g.integers(0, 4, 50)]).astype(np.uint8)
+    tC = np.tile(np.array([2, 2, 1, 0], np.uint8), 60)
+    qC = (3 - q[::-1]).astype(np.uint8)
+    assert len(_brute_hits(q, tB)) == 89 and not _brute_hits(qC, tC)
+    sts = [fr.candidate_stats(q, tA), fr.candidate_stats(q, tB), fr.candidate_stats(qC, tC)]
+    assert [s["nmode3"] for s in sts] == [1, 89, 0]
+    f = fr.read_features(sts, [0, 0, 1])
+    f32 = np.float32
+    b = fr.bf16_round
+    assert f[0, 39] == b(f32(-88) / f32(89)) and f[1, 39] == 0 and f[2, 39] == -1
+    assert f[0, 40] == b(f32(-85) / f32(89)) and f[1, 40] == 0 and f[2, 40] == -1
+    assert f[:, 41].tolist() == [0, 1, 0]
+    assert f[0, 42] == b(f32(1) / f32(3)) and f[1, 42] == 0 and f[2, 42] == b(f32(2) / f32(3))
+    assert (f[:, 43] == b(f32(88) / f32(89))).all()
+    assert (f[:, 44] == b(f32(3) / f32(16))).all()
+    assert f[:, 45].tolist() == b(np.array([0.3, 0.187, 0.24], np.float32)).tolist()
+    assert (f[:, 46] == b(f32(0.1))).all()
+    assert f[:, 47].tolist() == [0, 0, 1]
+    assert f[2, 48] == b(f32(180) / f32(240))
+
+
+def test_features_without_kmers_are_zero():
+    """A read shorter than 12 bases (P = 0) or a window shorter than 12 (J = 0)
+    has no hits: every hit feature is 0 (no division by P or J = 0), and the
+    single candidate is its read's argmax."""
+    g = np.random.default_rng(7)
+    t = g.integers(0, 4, 300).astype(np.uint8)
+    short = t[40:51].copy()                          # 11 bases: no 12-mer
+    st = fr.candidate_stats(short, t)
+    st2 = fr.candidate_stats(t[:100].copy(), t[:11].copy())
+    for s, m in ((st, 11), (st2, 100)):
+        f = fr.read_features([s], [0])[0]
+        assert np.isfinite(f).all()
+        # the only candidate holds the read's maximum (0), so f41 = 1
+        assert (f[:41] == 0).all() and f[41] == 1 and f[42] == 0 and f[43] == 0
+        assert f[44] == np.float32(1) / np.float32(16)
+        assert f[46] == fr.bf16_round(np.float32(m) / np.float32(1000))
