@@ -249,10 +249,26 @@ typedef struct {
 
 sw_status sw_mlp_create(sw_ctx *ctx, sw_mlp **out);
 sw_status sw_mlp_destroy(sw_ctx *ctx, sw_mlp *mlp);
-/* Copy SW_MLP_PARAMS host floats into the network; resets the Adam state. */
+/* Copy SW_MLP_PARAMS host floats into the network; resets the Adam state
+ * (moments and step count; sw_mlp_load restores them). */
 sw_status sw_mlp_set_params(sw_ctx *ctx, sw_mlp *mlp, const float *h_params);
 /* Copy the float32 master parameters to host memory (synchronous). */
 sw_status sw_mlp_get_params(sw_ctx *ctx, const sw_mlp *mlp, float *h_params);
+
+/* Checkpoint of the network with its optimiser state, so that training can stop
+ * and resume with bit-identical results: SW_MLP_STATE_BYTES bytes in a
+ * caller-owned HOST buffer, little-endian: 8 bytes "HPGSWMLP", uint32 format
+ * version (1), uint32 parameter count (SW_MLP_PARAMS), uint32 Adam step count,
+ * uint32 zero, then float32 parameters, first moments and second moments
+ * (SW_MLP_PARAMS each, parameter layout).  Both calls wait for the device and
+ * copy synchronously; they cannot be captured (SW_E_STATE).
+ * sw_mlp_save: SW_E_RANGE if cap < SW_MLP_STATE_BYTES.
+ * sw_mlp_load: SW_E_INVALID if len differs from SW_MLP_STATE_BYTES or the
+ * header is not this format (the network is then left unchanged); after a
+ * load, sw_mlp_train_step continues from the saved step. */
+#define SW_MLP_STATE_BYTES (24u + 12u * SW_MLP_PARAMS)
+sw_status sw_mlp_save(sw_ctx *ctx, const sw_mlp *mlp, void *h_buf, uint64_t cap);
+sw_status sw_mlp_load(sw_ctx *ctx, sw_mlp *mlp, const void *h_buf, uint64_t len);
 
 /* Features of every pair: d_feat[n_pairs * SW_FEATURES] (bfloat16 bits). */
 sw_status sw_features(sw_ctx *ctx, const sw_batch *batch, uint16_t *d_feat, void *stream);

@@ -96,6 +96,8 @@ def lib() -> ctypes.CDLL:
         L.sw_mlp_destroy.argtypes = [P, P]
         L.sw_mlp_set_params.argtypes = [P, P, P]
         L.sw_mlp_get_params.argtypes = [P, P, P]
+        L.sw_mlp_save.argtypes = [P, P, P, U64]
+        L.sw_mlp_load.argtypes = [P, P, P, U64]
         L.sw_features.argtypes = [P, ctypes.POINTER(sw_batch), P, P]
         L.sw_mlp_forward.argtypes = [P, P, P, U32, P, P]
         L.sw_mlp_grad.argtypes = [P, P, P, P, U32, P, P, P]
@@ -115,6 +117,7 @@ def lib() -> ctypes.CDLL:
                   "sw_graph_begin", "sw_graph_end", "sw_graph_launch", "sw_graph_destroy",
                   "sw_autotune",
                   "sw_mlp_destroy", "sw_mlp_set_params", "sw_mlp_get_params", "sw_features",
+                  "sw_mlp_save", "sw_mlp_load",
                   "sw_mlp_forward", "sw_mlp_grad", "sw_mlp_train_step", "sw_mlp_labels",
                   "sw_filter_candidates"):
             getattr(L, f).restype = ctypes.c_int
@@ -215,6 +218,22 @@ def sw_mlp_get_params(ctx, mlp) -> np.ndarray:
     a = np.zeros(SW_MLP_PARAMS, dtype=np.float32)
     _check(ctx, lib().sw_mlp_get_params(ctx, mlp, a.ctypes.data_as(ctypes.c_void_p)))
     return a
+
+
+SW_MLP_STATE_BYTES = 24 + 12 * SW_MLP_PARAMS
+
+
+def sw_mlp_save(ctx, mlp) -> bytes:
+    """Checkpoint of the network and its Adam state (SW_MLP_STATE_BYTES bytes)."""
+    buf = ctypes.create_string_buffer(SW_MLP_STATE_BYTES)
+    _check(ctx, lib().sw_mlp_save(ctx, mlp, ctypes.cast(buf, ctypes.c_void_p), len(buf)))
+    return buf.raw
+
+
+def sw_mlp_load(ctx, mlp, state: bytes):
+    """Restore a checkpoint written by sw_mlp_save."""
+    buf = ctypes.create_string_buffer(bytes(state), len(state))
+    _check(ctx, lib().sw_mlp_load(ctx, mlp, ctypes.cast(buf, ctypes.c_void_p), len(state)))
 
 
 def sw_features(ctx, batch, d_feat, stream=None):

@@ -884,6 +884,65 @@ sw_status sw_mlp_get_params(sw_ctx *ctx, const sw_mlp *mlp, float *h_params)
     return SW_OK;
 }
 
+namespace {
+
+constexpr char kMlpMagic[8] = {'H', 'P', 'G', 'S', 'W', 'M', 'L', 'P'};
+constexpr uint32_t kMlpVersion = 1;
+constexpr size_t kMlpHeader = 24;   // magic, version, parameter count, step, reserved
+static_assert(kMlpHeader + 12ull * kParams == SW_MLP_STATE_BYTES, "checkpoint layout");
+
+}  // namespace
+
+sw_status sw_mlp_save(sw_ctx *ctx, const sw_mlp *mlp, void *h_buf, uint64_t cap)
+{
+    if (!ctx || !mlp || !h_buf)
+        return fail(ctx, SW_E_INVALID, "NULL argument");
+    if (cap < SW_MLP_STATE_BYTES)
+        return fail(ctx, SW_E_RANGE, "checkpoint buffer holds %llu bytes, needs %llu",
+                    (unsigned long long)cap, (unsigned long long)SW_MLP_STATE_BYTES);
+    if (ctx->capturing)
+        return fail(ctx, SW_E_STATE, "sw_mlp_save cannot be captured");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    char *out = static_cast<char *>(h_buf);
+    const uint32_t head[4] = {kMlpVersion, (uint32_t)kParams, (uint32_t)mlp->step, 0u};
+    memcpy(out, kMlpMagic, 8);
+    memcpy(out + 8, head, sizeof head);
+    char *body = out + kMlpHeader;
+    HIP_TRY(ctx, hipMemcpy(body, mlp->theta, 4ull * kParams, hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(body + 4ull * kParams, mlp->m, 4ull * kParams, hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(body + 8ull * kParams, mlp->v, 4ull * kParams, hipMemcpyDeviceToHost));
+    return SW_OK;
+}
+
+sw_status sw_mlp_load(sw_ctx *ctx, sw_mlp *mlp, const void *h_buf, uint64_t len)
+{
+    if (!ctx || !mlp || !h_buf)
+        return fail(ctx, SW_E_INVALID, "NULL argument");
+    if (len != SW_MLP_STATE_BYTES)
+        return fail(ctx, SW_E_INVALID, "checkpoint of %llu bytes, expected %llu",
+                    (unsigned long long)len, (unsigned long long)SW_MLP_STATE_BYTES);
+    const char *in = static_cast<const char *>(h_buf);
+    uint32_t head[4];
+    memcpy(head, in + 8, sizeof head);
+    if (memcmp(in, kMlpMagic, 8) != 0 || head[0] != kMlpVersion || head[1] != (uint32_t)kParams ||
+        head[2] > 0x7FFFFFFFu)
+        return fail(ctx, SW_E_INVALID, "not a checkpoint of this network (magic, version, "
+                    "parameter count or step)");
+    if (ctx->capturing)
+        return fail(ctx, SW_E_STATE, "sw_mlp_load cannot be captured");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    const char *body = in + kMlpHeader;
+    HIP_TRY(ctx, hipMemcpy(mlp->theta, body, 4ull * kParams, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(mlp->m, body + 4ull * kParams, 4ull * kParams, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(mlp->v, body + 8ull * kParams, 4ull * kParams, hipMemcpyHostToDevice));
+    mlp->step = (int)head[2];
+    HIP_TRY(ctx, mlp_cast_params(mlp->theta, mlp->dev(), nullptr));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    return SW_OK;
+}
+
 sw_status sw_features(sw_ctx *ctx, const sw_batch *b, uint16_t *d_feat, void *stream)
 {
     if (!ctx)

@@ -25,12 +25,64 @@ serializes copies and compute (results stay the same).
 """
 from __future__ import annotations
 
+import json
+import os
+
 import numpy as np
 
 from . import (ALN_DTYPE, SW_WANT_ENDS, WINDOW_DTYPE, _ptr, sw_batch, sw_batch_score,
                sw_batch_traceback, sw_best_per_read, sw_filter_candidates, sw_pack2b)
 
 SCORING = (5, -4, -10, -1)
+
+
+class ChunkManifest:
+    """Which chunks of a stream have been handed out, kept in a JSON file so
+    that a stopped run (a failure, a kill) resumes where it stopped.
+
+    The file holds the run's identity (`key`, any JSON value the caller picks,
+    e.g. the input file names and chunk size), the number of chunks and the
+    sorted indices of the chunks whose results the consumer has received.  It
+    is rewritten after every chunk through a temporary file and an atomic
+    rename, so it is always either the old or the new record.  A chunk is
+    marked after its consumer returns: a run that stops between the two hands
+    that one chunk out again on resume (at least once), so a consumer should
+    treat a repeated chunk index as a replacement.  Opening an existing file of
+    another run (other key or chunk count) raises ValueError."""
+
+    def __init__(self, path: str, n_chunks: int, key=None):
+        self.path, self.n_chunks, self.key = path, int(n_chunks), key
+        self.done: set[int] = set()
+        if os.path.exists(path):
+            with open(path) as f:
+                rec = json.load(f)
+            if rec.get("n_chunks") != self.n_chunks or rec.get("key") != key:
+                raise ValueError(f"{path} records another run "
+                                 f"({rec.get('n_chunks')} chunks, key {rec.get('key')!r})")
+            self.done = {int(i) for i in rec.get("done", [])}
+        else:
+            self._write()
+
+    def pending(self) -> list[int]:
+        return [i for i in range(self.n_chunks) if i not in self.done]
+
+    @property
+    def complete(self) -> bool:
+        return len(self.done) == self.n_chunks
+
+    def mark(self, i: int):
+        if not 0 <= i < self.n_chunks:
+            raise IndexError(i)
+        self.done.add(int(i))
+        self._write()
+
+    def _write(self):
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump({"key": self.key, "n_chunks": self.n_chunks, "done": sorted(self.done)}, f)
+            f.flush()
+            os.fsync(f.fileno())
+        os.replace(tmp, self.path)
 
 
 class _View:
@@ -185,16 +237,50 @@ class StreamAligner:
         ho.pending = (idx, n)
         ds.free = ho.d2h
 
-    def run(self, chunks, consume=None):
-        """Process the HostChunk sequence `chunks` in order."""
+    def run(self, chunks, consume=None, manifest: ChunkManifest | None = None, hook=None):
+        """Process the HostChunk sequence `chunks` in order.
+
+        manifest: skip the chunks it records as handed out and record each chunk
+        once `consume` has returned, so that a run stopped by an exception can
+        be started again with the same manifest and only redoes the rest
+        (results are handed out with their index in `chunks`).  hook(i), when
+        given, is called on the host before chunk i's copies are issued (e.g. to
+        inject a failure); an exception from it, from `consume` or from a call
+        stops the run after the device has finished the work already issued."""
         import torch
-        consume = consume or (lambda i, r: None)
+        try:
+            self._run(chunks, consume, manifest, hook)
+        except BaseException:
+            torch.cuda.synchronize()      # no copy or kernel still uses the buffers
+            for ho in self.outs:
+                ho.pending = None
+            for ds in self.sets:
+                ds.free = None
+            raise
+
+    def _run(self, chunks, consume, manifest, hook):
+        import torch
+        user = consume or (lambda i, r: None)
+        if manifest is not None:
+            if manifest.n_chunks != len(chunks):
+                raise ValueError("the manifest is for another number of chunks")
+
+            def consume(i, r):
+                user(i, r)
+                manifest.mark(i)
+            todo = manifest.pending()
+        else:
+            consume = user
+            todo = list(range(len(chunks)))
         rc, bc, pc = self.caps
         prev = None            # (device set, chunk index, reads) computed, not yet copied out
-        for i, hc in enumerate(chunks):
+        for k, i in enumerate(todo):
+            hc = chunks[i]
             if hc.n_reads > rc or hc.n_bases > bc or hc.n_pairs > pc:
                 raise ValueError("chunk exceeds the stream's capacity")
-            ds = self.sets[i % 2]
+            if hook is not None:
+                hook(i)
+            ds = self.sets[k % 2]
             # host -> device, once the set's previous chunk has been copied out
             if ds.free is not None:
                 self.s_h2d.wait_event(ds.free)
@@ -209,20 +295,20 @@ class StreamAligner:
                 self._compute(ds, hc)
                 ds.done.record(self.s_comp)
             if prev is not None:
-                pds, pidx, pn = prev
-                ho = self.outs[pidx % 2]
-                # the pinned output set still holds chunk pidx - 2: hand it out first
+                pds, pk, pidx, pn = prev
+                ho = self.outs[pk % 2]
+                # the pinned output set still holds the chunk before: hand it out first
                 if ho.pending is not None:
                     self._hand_out(ho, consume)
                 self._copy_out(pds, ho, pidx, pn, after=ds.filtered)
-            prev = (ds, i, hc.n_reads)
+            prev = (ds, k, i, hc.n_reads)
         if prev is not None:
-            pds, pidx, pn = prev
-            ho = self.outs[pidx % 2]
+            pds, pk, pidx, pn = prev
+            ho = self.outs[pk % 2]
             if ho.pending is not None:
                 self._hand_out(ho, consume)
             self._copy_out(pds, ho, pidx, pn)
-        for k in range(len(chunks), len(chunks) + 2):
+        for k in range(len(todo), len(todo) + 2):
             ho = self.outs[k % 2]
             if ho.pending is not None:
                 self._hand_out(ho, consume)

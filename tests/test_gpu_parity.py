@@ -381,3 +381,26 @@ def test_config2_full_size_sampled(ctx):
     sel = np.sort(np.random.default_rng(1).choice(b.n_pairs, 20_000, replace=False)).astype(np.uint32)
     ref, _ = oracle.align_batch(b, SC, mode=0, sel=sel)
     assert (h["score"][sel] == ref["score"]).all()
+
+
+def test_traceback_scratch_too_small_marks_pairs(ctx):
+    """With a 1 MiB traceback budget the 1,025-2,048-base query class (64 lanes x
+    32 rows, whose code slot for a 1,100-base window is about 1.1 MiB) has no
+    room: its pairs get status bit 2 and score -1 and are not aligned, while
+    the 100-base pairs of the same call align exactly; with the default budget
+    every pair aligns."""
+    b = edge_batch(51, [100, 1500], [300, 1100], div=0.03)
+    ref, rops = oracle.align_batch(b, SC, mode=1)
+    m = b.read_len[b.windows["read_id"]]
+    small = m <= 100
+    sw.sw_ctx_set_option(ctx, sw.SW_OPT_TB_SCRATCH_MB, 1)
+    try:
+        a, o = gpu_traceback(ctx, b)
+    finally:
+        sw.sw_ctx_set_option(ctx, sw.SW_OPT_TB_SCRATCH_MB, 2048)
+    assert (a["status"][~small] == 4).all() and (a["score"][~small] == -1).all()
+    assert (a["n_ops"][~small] == 0).all()
+    idx = np.nonzero(small)[0]
+    assert_aln_equal(a[idx], o[idx], ref[idx], rops[idx])
+    a, o = gpu_traceback(ctx, b)
+    assert_aln_equal(a, o, ref, rops)

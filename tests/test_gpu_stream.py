@@ -75,3 +75,55 @@ def test_stream_matches_eager_and_oracle():
         sw.sw_mlp_destroy(ctx, mlp)
     finally:
         sw.sw_ctx_destroy(ctx)
+
+
+def test_stream_resumes_after_injected_failure(tmp_path):
+    """A host hook fails the run before chunk 5 of 6; restarting with the same
+    manifest processes only the chunks not yet handed out, and every chunk's
+    results equal those of an uninterrupted run, each handed out once."""
+    from paper_1304_0681_amd.stream import ChunkManifest
+    torch.cuda.set_device(0)
+    ctx = sw.sw_ctx_create(0)
+    try:
+        ref = synth.make_reference(synth.rng(synth.BASE_SEED + 105), 1_000_000)
+        b_tr = synth.paired_chunk(synth.BASE_SEED + 106, 3000, ref)
+        db_tr = sw.DeviceBatch.from_synth(ctx, b_tr)
+        p_tr = tr.plain_scores(ctx, db_tr)
+        feat, y = tr.features_and_labels(ctx, db_tr, p_tr)
+        mlp, _ = tr.train(ctx, feat, y, steps=200, batch=4096, seed=4)
+        thr = (-8.0, -4.0, -4.0)
+        chunks = [synth.paired_chunk(synth.BASE_SEED + 107 + k, 1000, ref) for k in range(2)]
+        hcs = [HostChunk(b) for b in chunks] * 3
+        st = StreamAligner(ctx, chunks[0].ref, mlp, thr, T_MAP, reads_cap=2000,
+                           bases_cap=2000 * 150, pairs_cap=2000 * 16, ops_stride=STRIDE)
+        full = {}
+        st.run(hcs, lambda i, r: full.__setitem__(i, r))
+        assert sorted(full) == list(range(6))
+        path = str(tmp_path / "stream.json")
+        got, calls = {}, []
+
+        def consume(i, r):
+            calls.append(i)
+            got[i] = r
+
+        def fail_before_5(i):
+            if i == 5:
+                raise RuntimeError("injected chunk failure")
+
+        with pytest.raises(RuntimeError, match="injected"):
+            st.run(hcs, consume, manifest=ChunkManifest(path, 6, key="t"), hook=fail_before_5)
+        first = sorted(calls)
+        assert 0 < len(first) < 6 and first == list(range(len(first)))
+        man = ChunkManifest(path, 6, key="t")
+        assert man.pending() == list(range(len(first), 6))
+        st.run(hcs, consume, manifest=man)
+        assert sorted(calls) == list(range(6))           # each chunk handed out once
+        assert man.complete
+        for i in range(6):
+            for f in ("best_score", "mapped", "pair", "kept"):
+                assert np.array_equal(got[i][f], full[i][f]), (i, f)
+            assert (got[i]["aln"] == full[i]["aln"]).all()
+            assert (got[i]["ops"] == full[i]["ops"]).all()
+        sw.sw_mlp_destroy(ctx, mlp)
+    finally:
+        sw.sw_ctx_destroy(ctx)
