@@ -153,6 +153,22 @@ sw_status sw_pack2b(sw_ctx *ctx, const uint8_t *d_ascii, uint64_t n, uint32_t *d
 sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *batch, const sw_scoring *sc,
                          uint32_t flags, sw_hit *d_hits, void *stream);
 
+/* Allocation-free variant of sw_batch_score, for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as sw_batch_score,
+ * and the same kernels; the scratch is a fixed array in the library's device
+ * memory (about 36 MiB on every GPU the library runs on, held until the
+ * process ends) instead of context scratch, and the call allocates nothing.
+ * Limits: n_pairs <= SW_NOALLOC_MAX_PAIRS (otherwise SW_E_RANGE); queries
+ * longer than 2,048 bases are scored by 8 waves (same results, slower).
+ * Every call on one GPU shares that array, which keeps the last call's
+ * contents (each call rebuilds everything it reads): calls that overlap on
+ * one GPU (two streams, contexts or threads) race and give undefined results,
+ * so the caller must serialise them. */
+#define SW_NOALLOC_MAX_PAIRS (1u << 22)
+sw_status sw_batch_score_noalloc(sw_ctx *ctx, const sw_batch *batch, const sw_scoring *sc,
+                                 uint32_t flags, sw_hit *d_hits, void *stream);
+
 /* Best hit per read (Sec. 2, stage E task iv): for every read, the pair with
  * the highest score among its windows (lowest pair index on ties) and that
  * score.  Reads without windows get best_pair 0xFFFFFFFF and score -1.

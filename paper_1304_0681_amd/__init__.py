@@ -22,6 +22,7 @@ SW_WANT_ENDS = 1
 SW_OPT_INT16 = 1
 SW_OPT_BLOCKS_PER_CU = 2
 SW_OPT_TB_SCRATCH_MB = 3
+SW_NOALLOC_MAX_PAIRS = 1 << 22
 OP_NAMES = "MIDNS"
 
 HIT_DTYPE = np.dtype([("score", "<i4"), ("read_end", "<i4"), ("ref_end", "<i4")])
@@ -83,6 +84,8 @@ def lib() -> ctypes.CDLL:
         L.sw_pack2b.argtypes = [P, P, U64, P, P, P]
         L.sw_batch_score.argtypes = [P, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scoring), U32,
                                      P, P]
+        L.sw_batch_score_noalloc.argtypes = [P, ctypes.POINTER(sw_batch),
+                                             ctypes.POINTER(sw_scoring), U32, P, P]
         L.sw_best_per_read.argtypes = [P, ctypes.POINTER(sw_batch), P, I32, P, P, P, P]
         L.sw_batch_traceback.argtypes = [P, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scoring),
                                          P, U32, P, P, U32, P, P]
@@ -112,6 +115,7 @@ def lib() -> ctypes.CDLL:
         L.sw_graph_launch.argtypes = [P, P, P]
         L.sw_graph_destroy.argtypes = [P, P]
         for f in ("sw_ctx_create", "sw_ctx_destroy", "sw_pack2b", "sw_batch_score",
+                  "sw_batch_score_noalloc",
                   "sw_best_per_read", "sw_batch_traceback", "sw_select_windows", "sw_cigar_string",
                   "sw_timing_enable", "sw_timing_get", "sw_ctx_set_option", "sw_mlp_create",
                   "sw_graph_begin", "sw_graph_end", "sw_graph_launch", "sw_graph_destroy",
@@ -161,6 +165,12 @@ def sw_pack2b(ctx, d_ascii, n, d_out, d_bad=None, stream=None):
 def sw_batch_score(ctx, batch, scoring, flags, d_hits, stream=None):
     _check(ctx, lib().sw_batch_score(ctx, ctypes.byref(batch.c), ctypes.byref(_sc(scoring)),
                                      int(flags), _ptr(d_hits), _stream_ptr(stream)))
+
+
+def sw_batch_score_noalloc(ctx, batch, scoring, flags, d_hits, stream=None):
+    """sw_batch_score on the library's static scratch (no device allocation)."""
+    _check(ctx, lib().sw_batch_score_noalloc(ctx, ctypes.byref(batch.c), ctypes.byref(_sc(scoring)),
+                                             int(flags), _ptr(d_hits), _stream_ptr(stream)))
 
 
 def sw_best_per_read(ctx, batch, d_hits, t_map, d_best_pair, d_best_score, d_mapped=None,

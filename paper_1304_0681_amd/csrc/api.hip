@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -48,6 +49,8 @@ struct sw_ctx {
     // graphs ended on this context and not yet destroyed: their kernel nodes hold
     // the current scratch pointers, so no scratch buffer may be freed or moved
     int live_graphs = 0;
+    // device address of the allocation-free call's static scratch (null: none)
+    void *static_scratch = nullptr;
     // filter scratch: read segments (first, last, count) and compaction offsets
     uint32_t *seg = nullptr;
     size_t seg_bytes = 0;
@@ -184,6 +187,43 @@ sw_status bucket_scratch(sw_ctx *ctx, uint32_t n_items, BucketScratch *s)
     return SW_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of sw_batch_score_noalloc: a file-scope device array, so that the
+// call needs no allocation.  Every GPU the library runs on holds its own copy
+// from module load until the process ends.  Layout: the bucketing scratch of
+// SW_NOALLOC_MAX_PAIRS pairs, then strip rows for kStaticStripWaves waves.
+// Host code never uses the array's name as an address (on the host it names a
+// stand-in, not device memory): sw_ctx_create looks its device address up once
+// per device with hipGetSymbolAddress, and only that address is passed on.
+// ---------------------------------------------------------------------------
+constexpr int kStaticStripWaves = 8;
+constexpr size_t kStaticStripOff = bucket_bytes(SW_NOALLOC_MAX_PAIRS);
+constexpr size_t kStaticBytes = kStaticStripOff + sizeof(int2) * 65536ull * kStaticStripWaves;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) uint8_t scratch[kStaticBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// Device address of `scratch` on the current device `dev`, looked up once.
+sw_status static_scratch_address(int dev, void **out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices)
+        return SW_OK;       // such devices simply have no allocation-free path
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, SW_E_DEVICE, "hipGetSymbolAddress(scratch): %s",
+                        hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return SW_OK;
+}
 
 }  // namespace
 
@@ -215,6 +255,11 @@ sw_status sw_ctx_create(int hip_device, sw_ctx **out)
     if (hipSetDevice(hip_device) != hipSuccess) {
         delete ctx;
         return fail(nullptr, SW_E_DEVICE, "device set-up failed");
+    }
+    const sw_status st = static_scratch_address(hip_device, &ctx->static_scratch);
+    if (st) {
+        delete ctx;
+        return st;
     }
     *out = ctx;
     return SW_OK;
@@ -384,6 +429,26 @@ sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
     return score_dispatch(ctx, b, sc, flags, d_hits, s, bs, ctx->strip_buf, ctx->strip_waves);
 }
 
+sw_status sw_batch_score_noalloc(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc,
+                                 uint32_t flags, sw_hit *d_hits, void *stream)
+{
+    bool work = false;
+    sw_status st = check_score_call(ctx, b, sc, flags, d_hits, &work);
+    if (st || !work)
+        return st;
+    if (b->n_pairs > SW_NOALLOC_MAX_PAIRS)
+        return fail(ctx, SW_E_RANGE, "sw_batch_score_noalloc takes at most %u pairs, got %u",
+                    SW_NOALLOC_MAX_PAIRS, b->n_pairs);
+    if (!ctx->static_scratch)
+        return fail(ctx, SW_E_STATE, "device %d has no static scratch (devices 0..%d only)",
+                    ctx->device, kMaxDevices - 1);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    BucketScratch bs;
+    carve_bucket(ctx->static_scratch, b->n_pairs, &bs);
+    int2 *strip = reinterpret_cast<int2 *>(static_cast<char *>(ctx->static_scratch) + kStaticStripOff);
+    return score_dispatch(ctx, b, sc, flags, d_hits, static_cast<hipStream_t>(stream), bs, strip,
+                          kStaticStripWaves);
+}
 
 sw_status sw_best_per_read(sw_ctx *ctx, const sw_batch *b, const sw_hit *d_hits, int32_t t_map,
                            uint32_t *d_best_pair, int32_t *d_best_score, uint8_t *d_mapped,
