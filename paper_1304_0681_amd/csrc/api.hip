@@ -20,7 +20,10 @@ const ClassShape kDefaultClasses[kNumClasses] = {
 int score_class_m_max(int cls) { return kDefaultClasses[cls].m_max; }
 
 // Packed int16 is dispatched only for the class and shape it is verified on
-// (queries of 65-100 bases, 4 lanes x 25 rows).
+// the GPU (queries of 65-100 bases, 4 lanes x 25 rows).  A call that ran the
+// packed kernel for every class did not return; the kernel's source, run on
+// the host for every shape on that call's pairs, is exact and in bounds, so
+// the cause lies outside what the source shows and the other shapes stay off.
 static bool packed_verified(int cls, const ClassShape &s) { return cls == 3 && s.G == 4 && s.RPL == 25; }
 
 }  // namespace hpgsw
@@ -384,9 +387,8 @@ sw_status score_dispatch(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
         const int mode = ends ? (wide ? 2 : 1) : 0;
         const int wpb = score_waves_per_block();
         const int grid = strip ? strip_waves / wpb : ctx->n_cu * ctx->blocks_per_cu[c];
-        // packed int16 when every score of the class fits 16 bits exactly.  Only
-        // the shapes in kPackedVerified run packed: a call that used the packed
-        // kernel for all classes did not return, and its cause is not known.
+        // packed int16 when every score of the class fits 16 bits exactly, on
+        // the shape verified on the GPU only (packed_verified)
         const bool packed = mode == 0 && ctx->int16 && !strip && sc->mismatch <= 0 &&
                             (int64_t)sc->match * kDefaultClasses[c].m_max <= 32767 &&
                             packed_verified(c, ctx->shapes[c]);
