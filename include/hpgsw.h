@@ -345,24 +345,32 @@ sw_status sw_filter_candidates(sw_ctx *ctx, const sw_batch *batch, const sw_mlp 
 #define SW_OPT_BLOCKS_PER_CU 2
 #define SW_OPT_TB_SCRATCH_MB 3
 
-/* Autotuning of the score kernels (the batching pattern's tile shapes).
- * Pairs are bucketed by query length into SW_NUM_CLASSES classes (upper
- * bounds 16, 32, 64, 100, 128, 160, 256, 512, 1024, 2048 and 65535 bases); each
- * class runs a persistent kernel whose tile is G lanes per pair x RPL query
- * rows per lane (G * RPL >= the class bound; the last class walks the query in
- * strips of 64 x 32 rows).  sw_autotune times, on the caller's sample batch,
- * every candidate (tile shape, workgroups per compute unit) of every class the
- * sample populates, `repeats` calls each with HIP events around each class's
- * kernel, and keeps the fastest per class in ctx for later sw_batch_score
- * calls (classes the sample leaves empty keep their defaults, path 0).
- * Candidate shapes for a class are the default shapes of that class and
- * of the next two (all exercised by the parity tests); workgroups per compute
- * unit are 1, 2 or 4.  Results are identical for every candidate: only time
- * changes.  out[SW_NUM_CLASSES] (host, may be NULL) receives the choice.
- * Synchronises the stream; not capturable; allocates a temporary hit buffer. */
+/* Autotuning of the score path (the batching pattern's buckets and tiles).
+ * Pairs are bucketed by query length into SW_NUM_CLASSES classes (default
+ * upper bounds 16, 32, 64, 100, 128, 160, 256, 512, 1024, 2048 and 65535
+ * bases); each class runs a persistent kernel whose tile is G lanes per pair x
+ * RPL query rows per lane (G * RPL >= the class bound; the last class walks
+ * the query in strips of 64 x 32 rows).  sw_autotune times the caller's sample
+ * batch (`repeats` calls per candidate, HIP events around each class's kernel)
+ * in two passes and keeps the result in ctx for later sw_batch_score calls:
+ *   1. class bounds: for each bound between two classes (the last two bounds
+ *      stay fixed), the candidates are the capacities of the default tiles
+ *      and the sample's query-length quantiles (10, 25, 50, 75, 90 %) between
+ *      its neighbours; a class whose bound exceeds its tile gets the smallest
+ *      default tile that holds it; a bound moves when the two classes it
+ *      separates get faster;
+ *   2. tiles: for every populated class, the three smallest tiles that hold
+ *      its bound, at 1, 2 or 4 workgroups per compute unit.
+ * The tiles searched are the classes' default tiles.  Results are identical
+ * for every candidate: only time changes.  Packed int16 runs on the 4 x 25
+ * tile of the 65-100-base class with its default bounds.  out[SW_NUM_CLASSES]
+ * (host, may be NULL) receives the choice (m_max: the tuned class bound).
+ * Synchronises the stream; not capturable; allocates a temporary hit buffer;
+ * the sample must have a host pair count.  The traceback keeps the default
+ * classes. */
 #define SW_NUM_CLASSES 11
 typedef struct {
-    int32_t m_max;          /* query-length bound of the class */
+    int32_t m_max;          /* query-length bound of the class (tuned) */
     int32_t G, RPL;         /* chosen tile: lanes per pair, rows per lane */
     int32_t blocks_per_cu;  /* chosen workgroups (4 waves) per compute unit */
     int32_t path;           /* 0 class not run, 1 int32, 2 int32 with ends, 3 packed int16 */
@@ -372,6 +380,21 @@ typedef struct {
 } sw_tune_entry;
 sw_status sw_autotune(sw_ctx *ctx, const sw_batch *sample, const sw_scoring *sc, uint32_t flags,
                       int repeats, sw_tune_entry *out, void *stream);
+
+/* sw_autotune with a persisted cache: a JSON-lines file at cache_path (host
+ * path) holding one object per tuning: {"key": ..., "edges": [...], "G": [...],
+ * "RPL": [...], "blocks_per_cu": [...], "path": [...], "candidates": [...],
+ * "ms": [...], "ms_default": [...]} (11 values each, by class).  The key names
+ * the device (architecture and compute units), the scoring, the flags and the
+ * sample's length profile (share of pairs per 8-base query-length bin and per
+ * 64-base window-length bin, in thousandths, and the order of magnitude of the
+ * pair count).  If the file holds a valid entry with this key (the last one
+ * wins), its choice is applied without timing and *cache_hit (may be NULL) is
+ * 1; otherwise the sample is tuned, the entry appended (the file is created if
+ * needed) and *cache_hit is 0.  SW_E_INVALID if the file cannot be written. */
+sw_status sw_autotune_cached(sw_ctx *ctx, const sw_batch *sample, const sw_scoring *sc,
+                             uint32_t flags, int repeats, const char *cache_path, int *cache_hit,
+                             sw_tune_entry *out, void *stream);
 sw_status sw_ctx_set_option(sw_ctx *ctx, int option, int value);
 
 /* Phase timing of sw_batch_score, from HIP events recorded on the call's

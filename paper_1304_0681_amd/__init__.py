@@ -110,6 +110,9 @@ def lib() -> ctypes.CDLL:
                                            ctypes.POINTER(sw_filter_params), P, P, P, P, P, P, P, P]
         L.sw_autotune.argtypes = [P, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scoring), U32,
                                   ctypes.c_int, P, P]
+        L.sw_autotune_cached.argtypes = [P, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scoring),
+                                         U32, ctypes.c_int, ctypes.c_char_p,
+                                         ctypes.POINTER(ctypes.c_int), P, P]
         L.sw_graph_begin.argtypes = [P, P]
         L.sw_graph_end.argtypes = [P, P, ctypes.POINTER(P)]
         L.sw_graph_launch.argtypes = [P, P, P]
@@ -119,7 +122,7 @@ def lib() -> ctypes.CDLL:
                   "sw_best_per_read", "sw_batch_traceback", "sw_select_windows", "sw_cigar_string",
                   "sw_timing_enable", "sw_timing_get", "sw_ctx_set_option", "sw_mlp_create",
                   "sw_graph_begin", "sw_graph_end", "sw_graph_launch", "sw_graph_destroy",
-                  "sw_autotune",
+                  "sw_autotune", "sw_autotune_cached",
                   "sw_mlp_destroy", "sw_mlp_set_params", "sw_mlp_get_params", "sw_features",
                   "sw_mlp_save", "sw_mlp_load",
                   "sw_mlp_forward", "sw_mlp_grad", "sw_mlp_train_step", "sw_mlp_labels",
@@ -298,6 +301,18 @@ def sw_autotune(ctx, batch, scoring, flags=0, repeats=3, stream=None):
                                   int(flags), int(repeats), ctypes.cast(out, ctypes.c_void_p),
                                   _stream_ptr(stream)))
     return [{f: getattr(e, f) for f, _ in sw_tune_entry._fields_} for e in out]
+
+
+def sw_autotune_cached(ctx, batch, scoring, cache_path, flags=0, repeats=3, stream=None):
+    """sw_autotune through the JSON-lines cache at `cache_path`; returns
+    (entries, cache_hit)."""
+    out = (sw_tune_entry * SW_NUM_CLASSES)()
+    hit = ctypes.c_int(0)
+    _check(ctx, lib().sw_autotune_cached(ctx, ctypes.byref(batch.c), ctypes.byref(_sc(scoring)),
+                                         int(flags), int(repeats), os.fsencode(cache_path),
+                                         ctypes.byref(hit), ctypes.cast(out, ctypes.c_void_p),
+                                         _stream_ptr(stream)))
+    return [{f: getattr(e, f) for f, _ in sw_tune_entry._fields_} for e in out], bool(hit.value)
 
 
 def sw_graph_begin(ctx, stream):

@@ -19,12 +19,12 @@ const ClassShape kDefaultClasses[kNumClasses] = {
 
 int score_class_m_max(int cls) { return kDefaultClasses[cls].m_max; }
 
-// Packed int16 is dispatched only for the class and shape it is verified on
-// the GPU (queries of 65-100 bases, 4 lanes x 25 rows).  A call that ran the
-// packed kernel for every class did not return; the kernel's source, run on
-// the host for every shape on that call's pairs, is exact and in bounds, so
-// the cause lies outside what the source shows and the other shapes stay off.
-static bool packed_verified(int cls, const ClassShape &s) { return cls == 3 && s.G == 4 && s.RPL == 25; }
+// Packed int16 is dispatched only for the shape it is verified on the GPU
+// (4 lanes x 25 rows).  A call that ran the packed kernel for every class did
+// not return; the kernel's source, run on the host for every shape on that
+// call's pairs, is exact and in bounds, so the cause lies outside what the
+// source shows and the other shapes stay off.
+static bool packed_verified(const ClassShape &s) { return s.G == 4 && s.RPL == 25; }
 
 }  // namespace hpgsw
 
@@ -59,6 +59,7 @@ struct sw_ctx {
     size_t seg_bytes = 0;
     ClassShape shapes[kNumClasses];
     int blocks_per_cu[kNumClasses];
+    ClassEdges edges;    // query-length class bounds of the score path
     bool int16 = true;   // packed int16 datapath where exact
     // phase timing: ev[0] before bucketing, ev[1] after it, ev[2 + c] after class c
     bool timing = false;
@@ -255,6 +256,7 @@ sw_status sw_ctx_create(int hip_device, sw_ctx **out)
         ctx->shapes[c] = kDefaultClasses[c];
         ctx->blocks_per_cu[c] = 2;
     }
+    ctx->edges = default_edges();
     if (hipSetDevice(hip_device) != hipSuccess) {
         delete ctx;
         return fail(nullptr, SW_E_DEVICE, "device set-up failed");
@@ -334,9 +336,17 @@ sw_status check_score_call(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc,
 }
 
 // Some read of the batch may exceed the largest single-strip class.
-bool batch_may_strip(const sw_batch *b)
+bool batch_may_strip(const sw_ctx *ctx, const sw_batch *b)
 {
-    return b->reads_len > (uint64_t)kDefaultClasses[kNumClasses - 2].m_max;
+    return b->reads_len > (uint64_t)ctx->edges.m_max[kNumClasses - 2];
+}
+
+// Packed int16 runs only as verified on the GPU: the 4 x 25 tile on the class
+// of queries of 65-100 bases (default bounds), where every score fits 16 bits.
+bool use_packed(const sw_ctx *ctx, int c, const sw_scoring *sc)
+{
+    return ctx->int16 && c == 3 && ctx->edges.m_max[2] == 64 && ctx->edges.m_max[3] == 100 &&
+           sc->mismatch <= 0 && (int64_t)sc->match * 100 <= 32767 && packed_verified(ctx->shapes[c]);
 }
 
 // Bucketing and the class kernels of one score call, on scratch the caller
@@ -346,10 +356,10 @@ sw_status score_dispatch(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
                          sw_hit *d_hits, hipStream_t s, const BucketScratch &bs, int2 *strip_buf,
                          int strip_waves)
 {
-    const bool may_strip = batch_may_strip(b);
+    const bool may_strip = batch_may_strip(ctx, b);
     if (ctx->timing)
         HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
-    HIP_TRY(ctx, launch_bucket(*b, nullptr, b->n_pairs, bs, d_hits, nullptr, s));
+    HIP_TRY(ctx, launch_bucket(*b, nullptr, b->n_pairs, bs, d_hits, nullptr, s, ctx->edges));
     if (ctx->timing)
         HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
     ScoreParams p;
@@ -375,7 +385,7 @@ sw_status score_dispatch(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
     for (int c = 0; c < kNumClasses; ++c) {
         const bool strip = c == kNumClasses - 1;
         const bool skip = (strip && !may_strip) ||
-                          (!strip && c > 0 && (uint64_t)kDefaultClasses[c - 1].m_max >= b->reads_len);
+                          (!strip && c > 0 && (uint64_t)ctx->edges.m_max[c - 1] >= b->reads_len);
         ctx->class_path[c] = 0;
         if (skip) {     // no read of this batch can fall in this class
             if (ctx->timing)
@@ -383,15 +393,11 @@ sw_status score_dispatch(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
             continue;
         }
         p.cls = c;
-        const bool wide = (int64_t)sc->match * kDefaultClasses[c].m_max >= 32768;
+        const bool wide = (int64_t)sc->match * ctx->edges.m_max[c] >= 32768;
         const int mode = ends ? (wide ? 2 : 1) : 0;
         const int wpb = score_waves_per_block();
         const int grid = strip ? strip_waves / wpb : ctx->n_cu * ctx->blocks_per_cu[c];
-        // packed int16 when every score of the class fits 16 bits exactly, on
-        // the shape verified on the GPU only (packed_verified)
-        const bool packed = mode == 0 && ctx->int16 && !strip && sc->mismatch <= 0 &&
-                            (int64_t)sc->match * kDefaultClasses[c].m_max <= 32767 &&
-                            packed_verified(c, ctx->shapes[c]);
+        const bool packed = mode == 0 && use_packed(ctx, c, sc);
         if (packed)
             HIP_TRY(ctx, launch_score16_class(ctx->shapes[c].G, ctx->shapes[c].RPL, p, grid, s));
         else
@@ -420,7 +426,7 @@ sw_status sw_batch_score(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, u
     BucketScratch bs;
     if ((st = bucket_scratch(ctx, b->n_pairs, &bs)))
         return st;
-    if (batch_may_strip(b) && !ctx->strip_buf) {
+    if (batch_may_strip(ctx, b) && !ctx->strip_buf) {
         if (ctx->capturing || ctx->live_graphs > 0)
             return fail(ctx, SW_E_STATE, "strip buffers needed during graph capture or while a "
                         "captured graph is alive: make the same calls once before capturing");
@@ -528,7 +534,7 @@ sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *b, const sw_scoring *s
     ctx->tb = static_cast<uint32_t *>(buf);
     ctx->tb_bytes = have;
     const TbBand band{d_hits, sc->match, -sc->gap_open, -sc->gap_extend};
-    HIP_TRY(ctx, launch_bucket(*b, d_pair_ids, n_sel, bs, nullptr, d_aln, s, band));
+    HIP_TRY(ctx, launch_bucket(*b, d_pair_ids, n_sel, bs, nullptr, d_aln, s, default_edges(), band));
     const int wpb = traceback_waves_per_block();
     const int grid = std::max(1, ctx->n_cu * 16 / wpb);
     for (int c = 0; c < kNumClasses; ++c) {
@@ -661,6 +667,92 @@ sw_status sw_timing_get(sw_ctx *ctx, sw_timing *out)
     return SW_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The tiles the autotuner may pick, as (capacity, G, RPL): the default tile
+// of every class, all of them run on the GPU by the parity tests.  (The 4 x 16
+// and 8 x 13 tiles are instantiated too; they stay out of the search, see the
+// design notes' list of what is switched off.)
+const ClassShape kShapes[] = {{16, 1, 16},   {32, 1, 32},   {64, 2, 32},   {100, 4, 25},
+                              {128, 4, 32},  {160, 8, 20},  {256, 8, 32},  {512, 16, 32},
+                              {1024, 32, 32}, {2048, 64, 32}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+struct TuneChoice {
+    ClassEdges edges;
+    ClassShape shapes[kNumClasses];
+    int bpc[kNumClasses];
+};
+
+TuneChoice current_choice(const sw_ctx *ctx)
+{
+    TuneChoice t;
+    t.edges = ctx->edges;
+    memcpy(t.shapes, ctx->shapes, sizeof t.shapes);
+    memcpy(t.bpc, ctx->blocks_per_cu, sizeof t.bpc);
+    return t;
+}
+
+void apply_choice(sw_ctx *ctx, const TuneChoice &t)
+{
+    ctx->edges = t.edges;
+    memcpy(ctx->shapes, t.shapes, sizeof t.shapes);
+    memcpy(ctx->blocks_per_cu, t.bpc, sizeof t.bpc);
+}
+
+TuneChoice default_choice()
+{
+    TuneChoice t;
+    t.edges = default_edges();
+    for (int c = 0; c < kNumClasses; ++c) {
+        t.shapes[c] = kDefaultClasses[c];
+        t.bpc[c] = 2;
+    }
+    return t;
+}
+
+// Smallest instantiated tile holding queries of up to m bases (the strip tile
+// for longer ones).
+ClassShape smallest_shape(int m)
+{
+    ClassShape best = kShapes[kNumShapes - 1];
+    for (const ClassShape &s : kShapes)
+        if (s.m_max >= m && s.m_max < best.m_max)
+            best = s;
+    return best;
+}
+
+// Time of every class of one score call of `b` under choice `t`, averaged over
+// `reps` calls (HIP events on the call's stream).
+sw_status time_choice(sw_ctx *ctx, const TuneChoice &t, const sw_batch *b, const sw_scoring *sc,
+                      uint32_t flags, sw_hit *hits, int reps, void *stream, float *ms, int *path)
+{
+    apply_choice(ctx, t);
+    for (int c = 0; c < kNumClasses; ++c) {
+        ms[c] = 0.f;
+        path[c] = 0;
+    }
+    for (int r = 0; r < reps; ++r) {
+        sw_timing tm;
+        sw_status st = sw_batch_score(ctx, b, sc, flags, hits, stream);
+        if (!st)
+            st = sw_timing_get(ctx, &tm);
+        if (st)
+            return st;
+        for (int c = 0; c < kNumClasses; ++c) {
+            ms[c] += tm.class_ms[c] / (float)reps;
+            path[c] = tm.class_path[c];
+        }
+    }
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint32_t flags,
                       int repeats, sw_tune_entry *out, void *stream)
 {
@@ -671,152 +763,176 @@ sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint
         return st;
     if ((st = check_scoring(ctx, sc)))
         return st;
+    if (flags & ~SW_WANT_ENDS)
+        return fail(ctx, SW_E_INVALID, "unknown flags 0x%x", flags);
     if (repeats < 1 || repeats > 100)
         return fail(ctx, SW_E_RANGE, "repeats must be in [1, 100]");
     if (ctx->capturing)
         return fail(ctx, SW_E_STATE, "sw_autotune cannot be captured");
+    if (b->d_n_pairs)
+        return fail(ctx, SW_E_INVALID, "sw_autotune takes a sample with a host pair count");
     static_assert(SW_NUM_CLASSES == kNumClasses, "class count of the ABI");
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    // candidates: default shapes of the class and the next two (rows cover the
-    // class), each at 1, 2 and 4 workgroups per compute unit
-    struct Cand {
-        ClassShape shape;
-        int bpc;
-    };
-    std::vector<Cand> cand[kNumClasses];
-    const int bpcs[3] = {1, 2, 4};
-    for (int c = 0; c < kNumClasses; ++c) {
-        std::vector<ClassShape> shapes;
-        const int last = c == kNumClasses - 1 ? c : std::min(c + 2, kNumClasses - 2);
-        for (int d = c; d <= last; ++d) {
-            ClassShape sh = kDefaultClasses[d];
-            sh.m_max = kDefaultClasses[c].m_max;
-            bool dup = false;
-            for (const ClassShape &o : shapes)
-                dup |= o.G == sh.G && o.RPL == sh.RPL;
-            if (!dup)
-                shapes.push_back(sh);
-        }
-        for (const ClassShape &sh : shapes)
-            for (int bpc : bpcs)
-                cand[c].push_back(Cand{sh, bpc});
-    }
-    size_t K = 0;
-    for (auto &v : cand)
-        K = std::max(K, v.size());
-    ClassShape keep_shapes[kNumClasses];
-    int keep_bpc[kNumClasses];
-    memcpy(keep_shapes, ctx->shapes, sizeof keep_shapes);
-    memcpy(keep_bpc, ctx->blocks_per_cu, sizeof keep_bpc);
+    const TuneChoice keep = current_choice(ctx);
     const bool was_timing = ctx->timing;
     void *hits = nullptr;
-    bool chosen = false;   // set once the tuned shapes are in ctx; every earlier exit restores
+    bool chosen = false;   // set once the tuned choice is in ctx; every earlier exit restores
     auto restore = [&]() {
         if (hits)
             (void)hipFree(hits);
         ctx->timing = was_timing;
         ctx->timed_call = false;
-        if (!chosen) {
-            memcpy(ctx->shapes, keep_shapes, sizeof keep_shapes);
-            memcpy(ctx->blocks_per_cu, keep_bpc, sizeof keep_bpc);
-        }
+        if (!chosen)
+            apply_choice(ctx, keep);
     };
+    auto bail = [&](sw_status e) {
+        restore();
+        return e;
+    };
+    const TuneChoice def = default_choice();
+    float def_ms[kNumClasses] = {}, cur_ms[kNumClasses] = {};
+    int def_path[kNumClasses] = {}, cur_path[kNumClasses] = {};
+    int n_cand[kNumClasses] = {};
+    TuneChoice cur = def;
     if (b->n_pairs) {
         const hipError_t e = hipMalloc(&hits, sizeof(sw_hit) * (size_t)b->n_pairs);
-        if (e != hipSuccess) {
-            restore();
-            return fail(ctx, SW_E_NOMEM, "sw_autotune: %s", hipGetErrorString(e));
-        }
-    }
-    if ((st = sw_timing_enable(ctx, 1))) {
-        restore();
-        return st;
-    }
-    uint32_t seg[2 * kNumClasses] = {};
-    float best_ms[kNumClasses], def_ms[kNumClasses];
-    int best_k[kNumClasses], best_path[kNumClasses], def_path[kNumClasses];
-    for (int c = 0; c < kNumClasses; ++c) {
-        best_ms[c] = 0.f;
-        def_ms[c] = 0.f;
-        best_k[c] = -1;
-        best_path[c] = 0;
-        def_path[c] = 0;
-    }
-    // k = -1: the defaults (also warms every kernel up)
-    for (int k = -1; k < (int)K && b->n_pairs; ++k) {
-        for (int c = 0; c < kNumClasses; ++c) {
-            if (k < 0) {
-                ctx->shapes[c] = kDefaultClasses[c];
-                ctx->blocks_per_cu[c] = 2;
-            } else {
-                const Cand &x = cand[c][std::min<size_t>((size_t)k, cand[c].size() - 1)];
-                ctx->shapes[c] = x.shape;
-                ctx->blocks_per_cu[c] = x.bpc;
-            }
-        }
-        float acc[kNumClasses] = {};
-        int path[kNumClasses] = {};
-        for (int rep = 0; rep < repeats + (k < 0 ? 1 : 0); ++rep) {
-            sw_timing t;
-            if ((st = sw_batch_score(ctx, b, sc, flags, static_cast<sw_hit *>(hits), stream)) ||
-                (st = sw_timing_get(ctx, &t))) {
-                restore();
-                return st;
-            }
-            if (k < 0 && rep == 0) {   // warm-up; read how many pairs each class holds
-                BucketScratch bs;
-                if ((st = bucket_scratch(ctx, b->n_pairs, &bs))) {
-                    restore();
-                    return st;
-                }
-                const hipError_t e = hipMemcpy(seg, bs.seg, sizeof seg, hipMemcpyDeviceToHost);
-                if (e != hipSuccess) {
-                    restore();
-                    return fail(ctx, SW_E_DEVICE, "sw_autotune: %s", hipGetErrorString(e));
-                }
+        if (e != hipSuccess)
+            return bail(fail(ctx, SW_E_NOMEM, "sw_autotune: %s", hipGetErrorString(e)));
+        if ((st = sw_timing_enable(ctx, 1)))
+            return bail(st);
+        // query length of every pair of the sample (host copies), for the
+        // candidate class edges at its length quantiles
+        std::vector<sw_window> win(b->n_pairs);
+        std::vector<uint16_t> rlen(b->n_reads);
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        HIP_TRY(ctx, hipMemcpy(win.data(), b->d_win, sizeof(sw_window) * win.size(),
+                               hipMemcpyDeviceToHost));
+        if (b->n_reads)
+            HIP_TRY(ctx, hipMemcpy(rlen.data(), b->d_read_len, 2ull * rlen.size(),
+                                   hipMemcpyDeviceToHost));
+        std::vector<int> lens;
+        lens.reserve(win.size());
+        for (const sw_window &w : win)
+            if (w.read_id < b->n_reads && rlen[w.read_id] > 0)
+                lens.push_back(rlen[w.read_id]);
+        std::sort(lens.begin(), lens.end());
+        // defaults (the first call also warms every kernel up)
+        if ((st = time_choice(ctx, def, b, sc, flags, (sw_hit *)hits, 1, stream, def_ms, def_path)) ||
+            (st = time_choice(ctx, def, b, sc, flags, (sw_hit *)hits, repeats, stream, def_ms,
+                              def_path)))
+            return bail(st);
+        memcpy(cur_ms, def_ms, sizeof cur_ms);
+        memcpy(cur_path, def_path, sizeof cur_path);
+        auto pairs_in = [&](uint32_t lo, uint32_t hi) {   // pairs with lo < m <= hi
+            return (size_t)(std::upper_bound(lens.begin(), lens.end(), (int)hi) -
+                            std::upper_bound(lens.begin(), lens.end(), (int)lo));
+        };
+        // 1. class edges: coordinate search over the bounds between classes k
+        //    and k + 1, candidates at the tile capacities and length quantiles
+        for (int k = 0; k + 2 < kNumClasses; ++k) {
+            const uint32_t lo = k ? cur.edges.m_max[k - 1] : 0u, hi = cur.edges.m_max[k + 1];
+            if (pairs_in(lo, hi) == 0)
                 continue;
+            std::vector<uint32_t> cands;
+            for (const ClassShape &sh : kShapes)
+                cands.push_back((uint32_t)sh.m_max);
+            for (double q : {0.1, 0.25, 0.5, 0.75, 0.9}) {
+                const size_t a = std::upper_bound(lens.begin(), lens.end(), (int)lo) - lens.begin();
+                const size_t z = std::upper_bound(lens.begin(), lens.end(), (int)hi) - lens.begin();
+                if (z > a)
+                    cands.push_back((uint32_t)lens[a + (size_t)(q * (double)(z - a - 1))]);
             }
-            for (int c = 0; c < kNumClasses; ++c) {
-                acc[c] += t.class_ms[c] / repeats;
-                path[c] = t.class_path[c];
+            std::sort(cands.begin(), cands.end());
+            cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
+            float best = cur_ms[k] + cur_ms[k + 1];
+            TuneChoice best_t = cur;
+            for (uint32_t e : cands) {
+                if (e <= lo || e >= hi || e == cur.edges.m_max[k] || e > 2048u)
+                    continue;
+                TuneChoice t = cur;
+                t.edges.m_max[k] = e;
+                if ((uint32_t)t.shapes[k].m_max < e || t.shapes[k].G * t.shapes[k].RPL < (int)e)
+                    t.shapes[k] = smallest_shape((int)e);
+                t.shapes[k].m_max = (int)e;
+                float ms[kNumClasses];
+                int path[kNumClasses];
+                if ((st = time_choice(ctx, t, b, sc, flags, (sw_hit *)hits, repeats, stream, ms, path)))
+                    return bail(st);
+                n_cand[k] += 1;
+                if (ms[k] + ms[k + 1] < best) {
+                    best = ms[k] + ms[k + 1];
+                    best_t = t;
+                    memcpy(cur_ms, ms, sizeof cur_ms);
+                    memcpy(cur_path, path, sizeof cur_path);
+                }
             }
+            cur = best_t;
         }
-        for (int c = 0; c < kNumClasses; ++c) {
-            if (k < 0) {
-                def_ms[c] = acc[c];
-                def_path[c] = path[c];
-            } else if ((size_t)k < cand[c].size() && (best_k[c] < 0 || acc[c] < best_ms[c])) {
-                best_ms[c] = acc[c];
-                best_k[c] = k;
-                best_path[c] = path[c];
+        // 2. tile and workgroups per compute unit of every populated class:
+        //    the three smallest tiles that hold the class, at 1, 2, 4 per CU
+        struct Cand {
+            ClassShape shape;
+            int bpc;
+        };
+        std::vector<Cand> cand[kNumClasses];
+        size_t K = 0;
+        for (int c = 0; c + 1 < kNumClasses; ++c) {
+            std::vector<ClassShape> fit;
+            for (const ClassShape &sh : kShapes)
+                if ((uint32_t)sh.m_max >= cur.edges.m_max[c])
+                    fit.push_back(sh);
+            std::sort(fit.begin(), fit.end(), [](const ClassShape &x, const ClassShape &y) {
+                return x.m_max < y.m_max || (x.m_max == y.m_max && x.G < y.G);
+            });
+            if (fit.size() > 3)
+                fit.resize(3);
+            for (ClassShape sh : fit) {
+                sh.m_max = (int)cur.edges.m_max[c];
+                for (int bpc : {1, 2, 4})
+                    cand[c].push_back(Cand{sh, bpc});
+            }
+            K = std::max(K, cand[c].size());
+        }
+        TuneChoice base = cur;
+        for (size_t k = 0; k < K; ++k) {
+            TuneChoice t = base;
+            for (int c = 0; c + 1 < kNumClasses; ++c) {
+                if (cand[c].empty())
+                    continue;
+                const Cand &x = cand[c][std::min(k, cand[c].size() - 1)];
+                t.shapes[c] = x.shape;
+                t.bpc[c] = x.bpc;
+            }
+            float ms[kNumClasses];
+            int path[kNumClasses];
+            if ((st = time_choice(ctx, t, b, sc, flags, (sw_hit *)hits, repeats, stream, ms, path)))
+                return bail(st);
+            for (int c = 0; c + 1 < kNumClasses; ++c) {
+                if (k >= cand[c].size() || !path[c])
+                    continue;
+                n_cand[c] += 1;
+                if (ms[c] < cur_ms[c]) {
+                    cur_ms[c] = ms[c];
+                    cur_path[c] = path[c];
+                    cur.shapes[c] = t.shapes[c];
+                    cur.bpc[c] = t.bpc[c];
+                }
             }
         }
     }
-    // keep the fastest candidate per class (the default if it was not beaten)
-    for (int c = 0; c < kNumClasses; ++c) {
-        ClassShape sh = kDefaultClasses[c];
-        int bpc = 2;
-        float ms = def_ms[c];
-        const bool populated = seg[2 * c + 1] > seg[2 * c];
-        int pth = populated ? def_path[c] : 0;
-        if (populated && best_k[c] >= 0 && best_ms[c] < def_ms[c]) {
-            sh = cand[c][best_k[c]].shape;
-            bpc = cand[c][best_k[c]].bpc;
-            ms = best_ms[c];
-            pth = best_path[c];
-        }
-        ctx->shapes[c] = sh;
-        ctx->blocks_per_cu[c] = bpc;
-        if (out) {
-            out[c].m_max = kDefaultClasses[c].m_max;
-            out[c].G = sh.G;
-            out[c].RPL = sh.RPL;
-            out[c].blocks_per_cu = bpc;
+    apply_choice(ctx, cur);
+    if (out) {
+        for (int c = 0; c < kNumClasses; ++c) {
+            const int pth = cur_path[c];
+            out[c].m_max = (int32_t)cur.edges.m_max[c];
+            out[c].G = cur.shapes[c].G;
+            out[c].RPL = cur.shapes[c].RPL;
+            out[c].blocks_per_cu = cur.bpc[c];
             out[c].path = pth;
-            out[c].candidates = (int32_t)cand[c].size();
-            out[c].ms = pth ? ms : 0.f;
-            out[c].ms_default = pth ? def_ms[c] : 0.f;
+            out[c].candidates = n_cand[c] + 1;
+            out[c].ms = pth ? cur_ms[c] : 0.f;
+            out[c].ms_default = def_path[c] ? def_ms[c] : 0.f;
         }
     }
     chosen = true;
@@ -824,6 +940,200 @@ sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint
     restore();
     if (e != hipSuccess)
         return fail(ctx, SW_E_DEVICE, "sw_autotune: %s", hipGetErrorString(e));
+    return SW_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603ull)
+{
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// Cache key of a tuning: the device (architecture, compute units), the scoring,
+// the flags, and the sample's length profile (share of pairs per query-length
+// bin of 8 bases and per window-length bin of 64 bases, in thousandths, and
+// the order of magnitude of the pair count).
+sw_status tune_key(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint32_t flags,
+                   std::string *key)
+{
+    std::vector<sw_window> win(b->n_pairs);
+    std::vector<uint16_t> rlen(b->n_reads);
+    if (b->n_pairs)
+        HIP_TRY(ctx, hipMemcpy(win.data(), b->d_win, sizeof(sw_window) * win.size(),
+                               hipMemcpyDeviceToHost));
+    if (b->n_reads)
+        HIP_TRY(ctx, hipMemcpy(rlen.data(), b->d_read_len, 2ull * rlen.size(), hipMemcpyDeviceToHost));
+    uint32_t hm[64] = {}, hn[32] = {};
+    size_t n = 0;
+    for (const sw_window &w : win) {
+        if (w.read_id >= b->n_reads)
+            continue;
+        hm[std::min<uint32_t>(rlen[w.read_id] / 8u, 63u)] += 1;
+        hn[std::min<uint32_t>(w.len / 64u, 31u)] += 1;
+        ++n;
+    }
+    uint16_t prof[96 + 1];
+    for (int i = 0; i < 64; ++i)
+        prof[i] = (uint16_t)(n ? (hm[i] * 1000ull + n / 2) / n : 0);
+    for (int i = 0; i < 32; ++i)
+        prof[64 + i] = (uint16_t)(n ? (hn[i] * 1000ull + n / 2) / n : 0);
+    int mag = 0;
+    while ((1ull << mag) < (unsigned long long)n)
+        ++mag;
+    prof[96] = (uint16_t)mag;
+    hipDeviceProp_t prop;
+    HIP_TRY(ctx, hipGetDeviceProperties(&prop, ctx->device));
+    char buf[256];
+    snprintf(buf, sizeof buf, "%.16s/%dcu/sc%d,%d,%d,%d/f%u/%016llx", prop.gcnArchName, ctx->n_cu,
+             sc->match, sc->mismatch, sc->gap_open, sc->gap_extend, flags,
+             (unsigned long long)fnv1a(prof, sizeof prof));
+    *key = buf;
+    return SW_OK;
+}
+
+// Numbers of the JSON array `"name":[...]` in `line` (false if absent or short).
+template <class T>
+bool json_array(const std::string &line, const char *name, T *out, int n)
+{
+    const std::string tag = std::string("\"") + name + "\":[";
+    size_t p = line.find(tag);
+    if (p == std::string::npos)
+        return false;
+    const char *c = line.c_str() + p + tag.size();
+    for (int i = 0; i < n; ++i) {
+        char *end = nullptr;
+        const double v = strtod(c, &end);
+        if (end == c)
+            return false;
+        out[i] = (T)v;
+        c = end;
+        while (*c == ' ' || *c == ',')
+            ++c;
+    }
+    return *c == ']';
+}
+
+}  // namespace
+
+extern "C" {
+
+sw_status sw_autotune_cached(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint32_t flags,
+                             int repeats, const char *cache_path, int *cache_hit,
+                             sw_tune_entry *out, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    if (!cache_path || !cache_path[0])
+        return fail(ctx, SW_E_INVALID, "cache_path is empty");
+    sw_status st = check_batch(ctx, b);
+    if (st)
+        return st;
+    if ((st = check_scoring(ctx, sc)))
+        return st;
+    if (ctx->capturing)
+        return fail(ctx, SW_E_STATE, "sw_autotune_cached cannot be captured");
+    if (b->d_n_pairs)
+        return fail(ctx, SW_E_INVALID, "sw_autotune_cached takes a sample with a host pair count");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    std::string key;
+    if ((st = tune_key(ctx, b, sc, flags, &key)))
+        return st;
+    if (cache_hit)
+        *cache_hit = 0;
+    // the last entry with this key wins
+    sw_tune_entry found[kNumClasses];
+    bool have = false;
+    if (FILE *f = fopen(cache_path, "r")) {
+        std::string line;
+        int ch;
+        while (true) {
+            line.clear();
+            while ((ch = fgetc(f)) != EOF && ch != '\n')
+                line.push_back((char)ch);
+            if (line.find("\"key\":\"" + key + "\"") != std::string::npos) {
+                int32_t edges[kNumClasses], G[kNumClasses], R[kNumClasses], bpc[kNumClasses],
+                    path[kNumClasses], nc[kNumClasses];
+                float ms[kNumClasses], msd[kNumClasses];
+                bool ok = json_array(line, "edges", edges, kNumClasses) &&
+                          json_array(line, "G", G, kNumClasses) &&
+                          json_array(line, "RPL", R, kNumClasses) &&
+                          json_array(line, "blocks_per_cu", bpc, kNumClasses) &&
+                          json_array(line, "path", path, kNumClasses) &&
+                          json_array(line, "candidates", nc, kNumClasses) &&
+                          json_array(line, "ms", ms, kNumClasses) &&
+                          json_array(line, "ms_default", msd, kNumClasses);
+                // a cached choice must be one this library can run
+                for (int c = 0; ok && c < kNumClasses; ++c) {
+                    ok = edges[c] >= 1 && edges[c] <= 65535 && (c == 0 || edges[c] > edges[c - 1]) &&
+                         (bpc[c] == 1 || bpc[c] == 2 || bpc[c] == 4) &&
+                         (c == kNumClasses - 1 ? edges[c] == 65535
+                                               : (score_shape_available(G[c], R[c]) &&
+                                                  G[c] * R[c] >= edges[c]));
+                }
+                if (ok) {
+                    for (int c = 0; c < kNumClasses; ++c)
+                        found[c] = sw_tune_entry{edges[c], G[c], R[c], bpc[c], path[c], nc[c], ms[c], msd[c]};
+                    have = true;
+                }
+            }
+            if (ch == EOF)
+                break;
+        }
+        fclose(f);
+    }
+    if (have) {
+        for (int c = 0; c < kNumClasses; ++c) {
+            ctx->edges.m_max[c] = (uint32_t)found[c].m_max;
+            if (c + 1 < kNumClasses)
+                ctx->shapes[c] = ClassShape{found[c].m_max, found[c].G, found[c].RPL};
+            ctx->blocks_per_cu[c] = found[c].blocks_per_cu;
+        }
+        if (out)
+            memcpy(out, found, sizeof found);
+        if (cache_hit)
+            *cache_hit = 1;
+        return SW_OK;
+    }
+    sw_tune_entry t[kNumClasses];
+    if ((st = sw_autotune(ctx, b, sc, flags, repeats, t, stream)))
+        return st;
+    if (out)
+        memcpy(out, t, sizeof t);
+    std::string line = "{\"key\":\"" + key + "\"";
+    auto arr = [&](const char *name, auto get) {
+        line += std::string(",\"") + name + "\":[";
+        for (int c = 0; c < kNumClasses; ++c) {
+            char v[32];
+            snprintf(v, sizeof v, "%s%.10g", c ? "," : "", (double)get(t[c]));
+            line += v;
+        }
+        line += "]";
+    };
+    arr("edges", [](const sw_tune_entry &x) { return x.m_max; });
+    arr("G", [](const sw_tune_entry &x) { return x.G; });
+    arr("RPL", [](const sw_tune_entry &x) { return x.RPL; });
+    arr("blocks_per_cu", [](const sw_tune_entry &x) { return x.blocks_per_cu; });
+    arr("path", [](const sw_tune_entry &x) { return x.path; });
+    arr("candidates", [](const sw_tune_entry &x) { return x.candidates; });
+    arr("ms", [](const sw_tune_entry &x) { return x.ms; });
+    arr("ms_default", [](const sw_tune_entry &x) { return x.ms_default; });
+    line += "}\n";
+    FILE *f = fopen(cache_path, "a");
+    if (!f)
+        return fail(ctx, SW_E_INVALID, "cannot open the tuning cache %s for appending", cache_path);
+    const bool wrote = fwrite(line.data(), 1, line.size(), f) == line.size();
+    const bool closed = fclose(f) == 0;
+    if (!wrote || !closed)
+        return fail(ctx, SW_E_INVALID, "cannot write the tuning cache %s", cache_path);
     return SW_OK;
 }
 

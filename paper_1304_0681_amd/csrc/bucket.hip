@@ -17,20 +17,15 @@ constexpr int kBlock = 256;
 constexpr int kItems = 16;                 // pairs per thread per block pass
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
-__device__ __forceinline__ int class_of(int m)
+// query-length class of a read: the first class whose upper bound holds it
+// (default bounds 16 32 64 100 128 160 256 512 1024 2048 65535)
+__device__ __forceinline__ int class_of(uint32_t m, const ClassEdges &e)
 {
-    // query-length class boundaries: 16 32 64 100 128 160 256 512 1024 2048 65535
-    if (m <= 16) return 0;
-    if (m <= 32) return 1;
-    if (m <= 64) return 2;
-    if (m <= 100) return 3;
-    if (m <= 128) return 4;
-    if (m <= 160) return 5;
-    if (m <= 256) return 6;
-    if (m <= 512) return 7;
-    if (m <= 1024) return 8;
-    if (m <= 2048) return 9;
-    return 10;
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < kNumClasses - 1; ++k)
+        c += m > e.m_max[k] ? 1 : 0;
+    return c;
 }
 
 __device__ __forceinline__ uint32_t len_bin(uint32_t n)
@@ -51,7 +46,8 @@ __device__ __forceinline__ void trivial(uint32_t k, int score, sw_hit *hits, sw_
 
 __device__ __forceinline__ uint32_t pair_bin(const sw_batch &b, const uint32_t *sel, uint32_t k,
                                              sw_hit *hits, sw_aln *aln, const TbBand &band,
-                                             uint32_t &n_out, uint32_t &m_out)
+                                             const ClassEdges &edges, uint32_t &n_out,
+                                             uint32_t &m_out)
 {
     const uint32_t p = sel ? sel[k] : k;
     n_out = 0;
@@ -85,7 +81,7 @@ __device__ __forceinline__ uint32_t pair_bin(const sw_batch &b, const uint32_t *
     }
     n_out = n;
     m_out = m;
-    return (uint32_t)class_of((int)m) * kBinsPerClass + len_bin(n);
+    return (uint32_t)class_of(m, edges) * kBinsPerClass + len_bin(n);
 }
 
 __global__ void __launch_bounds__(kBlock) k_zero(uint32_t *hist, uint32_t *maxlen)
@@ -99,7 +95,7 @@ __global__ void __launch_bounds__(kBlock) k_zero(uint32_t *hist, uint32_t *maxle
 __global__ void __launch_bounds__(kBlock) k_classify(sw_batch b, const uint32_t *sel, uint32_t n_items,
                                                      uint32_t *bin_out, uint32_t *hist,
                                                      uint32_t *maxlen, sw_hit *hits, sw_aln *aln,
-                                                     TbBand band)
+                                                     TbBand band, ClassEdges edges)
 {
     __shared__ uint32_t lh[kNumBins];
     __shared__ uint32_t lmax[2 * kNumClasses];
@@ -116,7 +112,7 @@ __global__ void __launch_bounds__(kBlock) k_classify(sw_batch b, const uint32_t 
         if (p >= n_items)
             break;
         uint32_t n = 0, m = 0;
-        const uint32_t bin = pair_bin(b, sel, (uint32_t)p, hits, aln, band, n, m);
+        const uint32_t bin = pair_bin(b, sel, (uint32_t)p, hits, aln, band, edges, n, m);
         bin_out[p] = bin;
         if (bin != kNone) {
             atomicAdd(&lh[bin], 1u);
@@ -207,16 +203,24 @@ __global__ void __launch_bounds__(kBlock) k_scatter(uint32_t n_pairs, const uint
 
 }  // namespace
 
+ClassEdges default_edges()
+{
+    ClassEdges e;
+    for (int c = 0; c < kNumClasses; ++c)
+        e.m_max[c] = (uint32_t)kDefaultClasses[c].m_max;
+    return e;
+}
+
 hipError_t launch_bucket(const sw_batch &b, const uint32_t *sel, uint32_t n_items,
                          const BucketScratch &s, sw_hit *hits, sw_aln *aln, hipStream_t st,
-                         const TbBand &band)
+                         const ClassEdges &edges, const TbBand &band)
 {
     hipLaunchKernelGGL(k_zero, dim3(64), dim3(kBlock), 0, st, s.hist, s.maxlen);
     const uint64_t per_block = (uint64_t)kBlock * kItems;
     const unsigned blocks = (unsigned)((n_items + per_block - 1) / per_block);
     if (n_items)
         hipLaunchKernelGGL(k_classify, dim3(blocks), dim3(kBlock), 0, st, b, sel, n_items, s.bin,
-                           s.hist, s.maxlen, hits, aln, band);
+                           s.hist, s.maxlen, hits, aln, band, edges);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, s.hist, s.seg, s.counter);
     if (n_items)
         hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(kBlock), 0, st, n_items,

@@ -31,6 +31,14 @@ struct ClassShape {
 // instantiated shape with the same or larger capacity.
 extern const ClassShape kDefaultClasses[kNumClasses];
 
+// Upper query-length bound of every class, as the bucketing kernel reads it
+// (increasing; the last is 65535).  The score path uses the context's edges,
+// which the autotuner may move; the traceback always uses the default ones.
+struct ClassEdges {
+    uint32_t m_max[kNumClasses];
+};
+ClassEdges default_edges();
+
 // Scratch words used by the bucketing and scheduling kernels.
 struct BucketScratch {
     uint32_t *bin;       // [n_pairs] bin of each pair (0xFFFFFFFF: resolved already)
@@ -100,7 +108,7 @@ hipError_t launch_pack2b(const uint8_t *ascii, uint64_t n, uint32_t *out, uint32
 // the band when `band.hits` is given.
 hipError_t launch_bucket(const sw_batch &b, const uint32_t *sel, uint32_t n_items,
                          const BucketScratch &s, sw_hit *hits, sw_aln *aln, hipStream_t st,
-                         const TbBand &band = TbBand{nullptr, 0, 0, 0});
+                         const ClassEdges &edges, const TbBand &band = TbBand{nullptr, 0, 0, 0});
 hipError_t launch_score_class(int cls, int G, int RPL, int mode, const ScoreParams &p, int grid,
                               hipStream_t st);
 int score_class_m_max(int cls);

@@ -1,0 +1,57 @@
+// Host stand-in for the few HIP runtime declarations the score kernels' source
+// uses, so that the unmodified kernel file compiles as plain C++ for the CPU
+// model of a wave (tests/host_model/score_model.cpp).  Kernel launches compile
+// to nothing; the model calls the kernel functions itself, one thread per
+// lane.  Cross-lane operations and the AMDGPU builtins the kernels use are
+// declared here and defined by the model.
+#pragma once
+
+#include <stdint.h>
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline __attribute__((always_inline))
+#define __launch_bounds__(...)
+
+typedef int hipError_t;
+enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
+typedef struct ihipStream_t *hipStream_t;
+
+struct dim3 {
+    unsigned x, y, z;
+    dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+#define hipLaunchKernelGGL(...) ((void)0)
+inline hipError_t hipGetLastError() { return hipSuccess; }
+
+struct int2 {
+    int x, y;
+};
+inline int2 make_int2(int x, int y) { return int2{x, y}; }
+
+struct ModelIdx {
+    unsigned x, y, z;
+};
+extern thread_local ModelIdx threadIdx, blockIdx;
+
+inline int max(int a, int b) { return a > b ? a : b; }
+inline int min(int a, int b) { return a < b ? a : b; }
+inline unsigned max(unsigned a, unsigned b) { return a > b ? a : b; }
+inline unsigned min(unsigned a, unsigned b) { return a < b ? a : b; }
+inline uint64_t min(uint64_t a, uint64_t b) { return a < b ? a : b; }
+
+int model_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl);
+int __shfl(int v, int src, int width = 64);
+int __shfl_xor(int v, int mask, int width = 64);
+uint64_t __shfl_xor(uint64_t v, int mask, int width = 64);
+uint32_t atomicAdd(uint32_t *p, uint32_t v);
+uint32_t model_perm(uint32_t hi, uint32_t lo, uint32_t sel);
+uint32_t model_alignbit(uint32_t hi, uint32_t lo, uint32_t shift);
+int model_sbfe(int src, int offset, int width);
+inline void __threadfence_block() {}
+
+#define __builtin_amdgcn_update_dpp model_update_dpp
+#define __builtin_amdgcn_perm model_perm
+#define __builtin_amdgcn_alignbit model_alignbit
+#define __builtin_amdgcn_sbfe model_sbfe

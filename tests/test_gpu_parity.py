@@ -340,7 +340,7 @@ def test_short_reads_with_gaps(ctx):
 @pytest.mark.skip(reason="packed int16 kernels other than the 4-lane x 25-row shape are switched "
                          "off: a call that ran them for every query class did not return on the "
                          "GPU; the kernel's own source, run on the host for every shape on this "
-                         "batch (test_score16_host_model.py), is exact and in bounds, so no cause "
+                         "batch (test_score_host_model.py), is exact and in bounds, so no cause "
                          "in the source is established and the case stays off the GPU")
 def test_packed_int16_all_classes(ctx):
     b = edge_batch(11, EDGE_M, EDGE_N)
