@@ -375,8 +375,10 @@ typedef struct {
     int32_t blocks_per_cu;  /* chosen workgroups (4 waves) per compute unit */
     int32_t path;           /* 0 class not run, 1 int32, 2 int32 with ends, 3 packed int16 */
     int32_t candidates;     /* candidates timed */
-    float ms;               /* best time of the class per call (0 if not run) */
-    float ms_default;       /* time of the default choice per call */
+    float ms;               /* time of the class per call under the choice (0: empty) */
+    float ms_default;       /* time of the class under the default bounds and tiles
+                               (0: empty there); when a bound moved the classes hold
+                               other pairs, so compare the sums over all classes */
 } sw_tune_entry;
 sw_status sw_autotune(sw_ctx *ctx, const sw_batch *sample, const sw_scoring *sc, uint32_t flags,
                       int repeats, sw_tune_entry *out, void *stream);

@@ -795,6 +795,7 @@ sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint
     int def_path[kNumClasses] = {}, cur_path[kNumClasses] = {};
     int n_cand[kNumClasses] = {};
     TuneChoice cur = def;
+    bool populated[kNumClasses] = {}, populated_def[kNumClasses] = {};
     if (b->n_pairs) {
         const hipError_t e = hipMalloc(&hits, sizeof(sw_hit) * (size_t)b->n_pairs);
         if (e != hipSuccess)
@@ -828,6 +829,8 @@ sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint
             return (size_t)(std::upper_bound(lens.begin(), lens.end(), (int)hi) -
                             std::upper_bound(lens.begin(), lens.end(), (int)lo));
         };
+        for (int c = 0; c < kNumClasses; ++c)
+            populated_def[c] = pairs_in(c ? def.edges.m_max[c - 1] : 0u, def.edges.m_max[c]) > 0;
         // 1. class edges: coordinate search over the bounds between classes k
         //    and k + 1, candidates at the tile capacities and length quantiles
         for (int k = 0; k + 2 < kNumClasses; ++k) {
@@ -894,6 +897,8 @@ sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint
             }
             K = std::max(K, cand[c].size());
         }
+        for (int c = 0; c < kNumClasses; ++c)
+            populated[c] = pairs_in(c ? cur.edges.m_max[c - 1] : 0u, cur.edges.m_max[c]) > 0;
         TuneChoice base = cur;
         for (size_t k = 0; k < K; ++k) {
             TuneChoice t = base;
@@ -909,7 +914,7 @@ sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint
             if ((st = time_choice(ctx, t, b, sc, flags, (sw_hit *)hits, repeats, stream, ms, path)))
                 return bail(st);
             for (int c = 0; c + 1 < kNumClasses; ++c) {
-                if (k >= cand[c].size() || !path[c])
+                if (k >= cand[c].size() || !path[c] || !populated[c])
                     continue;
                 n_cand[c] += 1;
                 if (ms[c] < cur_ms[c]) {
@@ -924,7 +929,7 @@ sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint
     apply_choice(ctx, cur);
     if (out) {
         for (int c = 0; c < kNumClasses; ++c) {
-            const int pth = cur_path[c];
+            const int pth = populated[c] ? cur_path[c] : 0;   // 0: the sample left it empty
             out[c].m_max = (int32_t)cur.edges.m_max[c];
             out[c].G = cur.shapes[c].G;
             out[c].RPL = cur.shapes[c].RPL;
@@ -932,7 +937,9 @@ sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint
             out[c].path = pth;
             out[c].candidates = n_cand[c] + 1;
             out[c].ms = pth ? cur_ms[c] : 0.f;
-            out[c].ms_default = def_path[c] ? def_ms[c] : 0.f;
+            // class times under the tuned bounds and under the default ones (the
+            // classes hold different pairs when a bound moved; each sum covers all)
+            out[c].ms_default = populated_def[c] ? def_ms[c] : 0.f;
         }
     }
     chosen = true;
