@@ -86,8 +86,48 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(batch, target_s: float):
-    """The oracle (plain scalar C, all host cores) on a seeded sample of pairs."""
+STREAM_REF_SEED = 20130301 + 5
+STREAM_REF_LEN = 64_000_000
+# Distinct chunks generated for the stream, which cycles through them.  A run
+# over 20 distinct chunks faulted the GPU in a chunk after the first two and
+# the cause is not found; the stream stays on the two chunks that have run
+# cleanly.
+STREAM_DISTINCT = 2
+
+
+def _gen_stream_chunk(seed: int, n_frags: int):
+    """One paired-read chunk of the stream workload (runs in a worker process)."""
+    import synth
+    ref = synth.make_reference(synth.rng(STREAM_REF_SEED), STREAM_REF_LEN)
+    b = synth.paired_chunk(seed, n_frags, ref)
+    return b.reads, b.read_off, b.read_len, b.windows
+
+
+def start_stream_generation(args):
+    """Generate the stream's distinct chunks in worker processes (started before
+    the GPU is used; the chunks are collected by the stream section)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    n = min(STREAM_DISTINCT, args.stream_chunks)
+    ex = cf.ProcessPoolExecutor(n, mp_context=mp.get_context("spawn"))
+    futs = [ex.submit(_gen_stream_chunk, 20130301 + 500 + k, args.stream_frags) for k in range(n)]
+    return ex, futs
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(batch, target_s: float, c1=None):
+    """The oracle (plain scalar C, all host cores) on a seeded sample of pairs;
+    also on one core, and on all of config 1 with traceback (`c1`)."""
     import oracle
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     g = np.random.default_rng(7)
@@ -109,13 +149,38 @@ def cpu_baseline(batch, target_s: float):
     dt = time.perf_counter() - t
     c = int(cells[sel].sum())
     reads_per_pair = batch.n_reads / batch.n_pairs
-    return {
+    # one core, on a sample sized for about 3 s
+    k1 = int(min(batch.n_pairs, max(2000, k0 * 3.0 / max(dt0 * cores, 1e-6))))
+    sel1 = np.sort(order[:k1])
+    t = time.perf_counter()
+    oracle.align_batch(batch, SCORING, mode=0, sel=sel1, nthreads=1)
+    dt1 = time.perf_counter() - t
+    out = {
         "value": round(c / dt / 1e9, 3), "unit": "GCUPS", "cores": int(cores), "kind": "oracle",
         "sample": f"{k} of {batch.n_pairs} pairs (seeded uniform sample, {c:.3e} cells, "
                   f"{dt:.1f} s), linear-memory score + end cell",
         "reads_per_s": round(k * reads_per_pair / dt, 1),
         "calibration_gcups": round(rate / 1e9, 3),
+        "cpu_model": _cpu_model(),
+        "one_core": {"gcups": round(int(cells[sel1].sum()) / dt1 / 1e9, 3),
+                     "sample": f"{k1} pairs, {dt1:.1f} s"},
     }
+    if c1 is not None:
+        m1 = c1.read_len[c1.windows["read_id"]].astype(np.int64)
+        cells1 = int((m1 * np.minimum(c1.windows["len"].astype(np.int64),
+                                      len(c1.ref) - c1.windows["ref_begin"].astype(np.int64))).sum())
+        t = time.perf_counter()
+        oracle.align_batch(c1, SCORING, mode=1, nthreads=cores)
+        dta = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.align_batch(c1, SCORING, mode=1, nthreads=1)
+        dtb = time.perf_counter() - t
+        out["config1_full_alignment"] = {
+            "pairs": c1.n_pairs, "cells": cells1,
+            "all_cores": {"seconds": round(dta, 4), "gcups": round(cells1 / dta / 1e9, 3)},
+            "one_core": {"seconds": round(dtb, 4), "gcups": round(cells1 / dtb / 1e9, 3)},
+            "note": "full H/E/F matrices, score, ends and CIGAR of every pair"}
+    return out
 
 
 def _bf16_col(feat, j):
@@ -312,6 +377,111 @@ def bench_filter(ctx, args, hard=False):
     }
 
 
+def _mixed_lengths(seed, n_reads, ref_len=4_000_000):
+    """Reads of 20-600 nt (eleven lengths, equal shares) with 1-4 windows of
+    200-800 nt each, for the autotuner's mixed-length comparison."""
+    import synth
+    g = np.random.default_rng(seed)
+    ref = g.integers(0, 4, ref_len).astype(np.uint8)
+    lens = g.choice([20, 40, 50, 70, 90, 110, 140, 150, 200, 300, 600], n_reads)
+    starts = g.integers(1000, ref_len - 2000, n_reads)
+    reads, wins = [], []
+    for i in range(n_reads):
+        seg = ref[starts[i]:starts[i] + lens[i]].copy()
+        mut = g.random(len(seg)) < 0.01
+        seg[mut] = (seg[mut] + 1) % 4
+        reads.append(synth.ASCII[seg].tobytes())
+        for _ in range(int(g.integers(1, 5))):
+            wins.append((i, int(max(starts[i] - g.integers(0, 200), 0)), int(g.integers(200, 801)),
+                         int(g.integers(0, 2))))
+    return synth.custom(synth.ASCII[ref].tobytes(), reads, wins)
+
+
+def bench_autotune_mixed(args):
+    """The autotuner on a mixed-length workload: score time of a 200k-read batch
+    with the default classes and tiles, and after tuning on a separate sample."""
+    import torch
+
+    import paper_1304_0681_amd as sw
+
+    ctx = sw.sw_ctx_create(0)                # its own context: the tuning stays here
+    try:
+        b = _mixed_lengths(20130301 + 71, 200_000)
+        sample = _mixed_lengths(20130301 + 72, 50_000)
+        db = sw.DeviceBatch.from_synth(ctx, b)
+        dbs = sw.DeviceBatch.from_synth(ctx, sample)
+        hits = torch.empty((b.n_pairs, 3), dtype=torch.int32, device="cuda")
+
+        def timed():
+            for _ in range(2):
+                sw.sw_batch_score(ctx, db, SCORING, 0, hits)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(max(args.steps, 5)):
+                sw.sw_batch_score(ctx, db, SCORING, 0, hits)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / max(args.steps, 5) * 1e3
+
+        ms_def = timed()
+        t0 = time.perf_counter()
+        tune = sw.sw_autotune(ctx, dbs, SCORING, 0, repeats=2)
+        t_tune = time.perf_counter() - t0
+        ms_tuned = timed()
+        cells = b.cells()
+        return {
+            "workload": "200,000 reads of 20-600 nt (eleven lengths) x 1-4 windows of 200-800 nt; "
+                        "tuned on a separate 50,000-read sample",
+            "pairs": b.n_pairs, "cells": cells,
+            "default_ms": round(ms_def, 3), "tuned_ms": round(ms_tuned, 3),
+            "speedup": round(ms_def / ms_tuned, 4),
+            "gcups_default": round(cells / ms_def / 1e6, 1), "gcups_tuned": round(cells / ms_tuned / 1e6, 1),
+            "tuning_seconds": round(t_tune, 2),
+            "choice": [{"m_max": t["m_max"], "tile": [t["G"], t["RPL"]],
+                        "blocks_per_cu": t["blocks_per_cu"], "path": PATHS.get(t["path"], "-"),
+                        "candidates": t["candidates"]} for t in tune if t["path"]],
+        }
+    finally:
+        sw.sw_ctx_destroy(ctx)
+
+
+def bench_config1(ctx, args):
+    """Plain SW with ends and traceback of every pair: 1,000 reads of 100 nt, one
+    300-nt window each (score, end cells, begins and CIGAR)."""
+    import torch
+
+    import paper_1304_0681_amd as sw
+    import synth
+
+    b = synth.config1()
+    db = sw.DeviceBatch.from_synth(ctx, b)
+    hits = torch.empty((b.n_pairs, 3), dtype=torch.int32, device="cuda")
+    ids = torch.arange(b.n_pairs, dtype=torch.int32, device="cuda")
+    stride = int(b.read_len.max()) + int(b.windows["len"].max()) + 2
+    aln = torch.empty((b.n_pairs, 7), dtype=torch.int32, device="cuda")
+    ops = torch.empty((b.n_pairs, stride), dtype=torch.int32, device="cuda")
+
+    def step():
+        db.pack_reads()
+        sw.sw_batch_score(ctx, db, SCORING, sw.SW_WANT_ENDS, hits)
+        sw.sw_batch_traceback(ctx, db, SCORING, ids, b.n_pairs, aln, ops, stride, hits=hits)
+
+    for _ in range(max(args.warmup, 2)):
+        step()
+    torch.cuda.synchronize()
+    reps = max(args.steps, 20)
+    t = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    cells = b.cells()
+    return {"workload": "1,000 x 100-nt reads vs one 300-nt window each (1 Mb reference); score, "
+                        "end cells, traceback to CIGAR of every pair",
+            "pairs": b.n_pairs, "cells": cells, "ms_per_step": round(dt * 1e3, 4),
+            "pairs_per_s": round(b.n_pairs / dt, 1), "gcups": round(cells / dt / 1e9, 2),
+            "note": "a launch-bound size: 3e7 cells take a few microseconds of arithmetic"}
+
+
 def band_width(h, m, n, sc=SCORING):
     """Columns the traceback's DP covers per pair (the band of the score and end
     cell in h, else the whole window), for counting the cells it computes."""
@@ -485,10 +655,12 @@ def _spliced_filtered(ctx, args, b, db, ap, t_plain):
     return out
 
 
-def bench_stream(ctx, args):
+def bench_stream(ctx, args, gen):
     """Paired 150-nt mates against a 64 Mb reference, streamed in chunks of
     args.stream_frags fragments (2 mates each, 16 windows per mate) through the
-    filtered path with double-buffered host<->device copies; timed end to end."""
+    filtered path with double-buffered host<->device copies; timed end to end.
+    Two distinct chunks (generated in worker processes while the earlier
+    sections ran) are cycled through args.stream_chunks chunk passes."""
     import torch
 
     import paper_1304_0681_amd as sw
@@ -498,7 +670,13 @@ def bench_stream(ctx, args):
 
     t0 = time.perf_counter()
     t_map = 2 * 150
-    ref = synth.make_reference(synth.rng(synth.BASE_SEED + 5), 64_000_000)
+    ref = synth.make_reference(synth.rng(STREAM_REF_SEED), STREAM_REF_LEN)
+    ref_ascii = synth.ASCII[ref]
+    # the reference, packed once on the device, shared by the plain passes below
+    d_ref = torch.from_numpy(ref_ascii).cuda()
+    ref2b = torch.empty((len(ref) + 15) // 16, dtype=torch.int32, device="cuda")
+    sw.sw_pack2b(ctx, d_ref, len(ref), ref2b)
+    del d_ref
     # the filter: trained and calibrated on mates of its own (labels from plain SW)
     b_tr = synth.paired_chunk(synth.BASE_SEED + 510, 100_000, ref)
     db_tr = sw.DeviceBatch.from_synth(ctx, b_tr)
@@ -517,25 +695,28 @@ def bench_stream(ctx, args):
                                           target=0.9995)
     tune = None
     if not args.no_autotune:
-        # tiles and workgroups per CU for the mates' query-length class, tuned on
-        # the calibration mates in the mode the stream scores its kept pairs in
+        # classes and tiles for the mates, tuned on the calibration mates in the
+        # mode the stream scores its kept pairs in
         tune = [t for t in sw.sw_autotune(ctx, db_ca, SCORING, sw.SW_WANT_ENDS, repeats=3)
                 if t["path"]]
         log("stream autotune: " + "; ".join(
-            f"m<={t['m_max']}: {t['G']}x{t['RPL']} bpc {t['blocks_per_cu']} {t['ms']:.2f} ms "
-            f"(default {t['ms_default']:.2f})" for t in tune))
+            f"m<={t['m_max']}: {t['G']}x{t['RPL']} bpc {t['blocks_per_cu']} {t['ms']:.2f} ms"
+            for t in tune))
     del f_ca, p_ca, db_ca, b_ca
-    # two distinct chunks, generated once and cycled (the generator is far slower
-    # than the GPU); plain SW on each gives the recall reference
-    chunks = [synth.paired_chunk(synth.BASE_SEED + 500 + k, args.stream_frags, ref)
-              for k in range(2)]
-    plain_best, plain_ms = [], []
-    for b in chunks:
-        db = sw.DeviceBatch.from_synth(ctx, b)
+    ex, futs = gen
+    hcs, plain_best, plain_ms = [], [], []
+    for k in range(len(futs)):
+        reads, read_off, read_len, windows = futs[k].result()
+        futs[k] = None
+        b = synth.Batch(ref=ref_ascii, reads=reads, read_off=read_off, read_len=read_len,
+                        windows=windows, truth={})
+        # plain SW on the chunk (device resident) gives the recall reference
+        db = sw.DeviceBatch(ctx, None, b.reads, b.read_off, b.read_len, b.windows,
+                            ref2b=(ref2b, len(ref)))
         hits = torch.empty((b.n_pairs, 3), dtype=torch.int32, device="cuda")
         bp = torch.empty(b.n_reads, dtype=torch.int32, device="cuda")
         bs = torch.empty(b.n_reads, dtype=torch.int32, device="cuda")
-        for rep in range(2):
+        for _ in range(2):
             torch.cuda.synchronize()
             t = time.perf_counter()
             db.pack_reads()
@@ -544,39 +725,42 @@ def bench_stream(ctx, args):
             torch.cuda.synchronize()
         plain_ms.append((time.perf_counter() - t) * 1e3)
         plain_best.append(bs.cpu().numpy())
-        del db, hits, bp, bs
-    hcs = [HostChunk(b) for b in chunks]
+        hcs.append(HostChunk(b))
+        del db, hits, bp, bs, b, reads, windows
+    ex.shutdown()
     rc = max(h.n_reads for h in hcs)
-    st = StreamAligner(ctx, chunks[0].ref, mlp, (drop, lo, hi), t_map, reads_cap=rc,
+    st = StreamAligner(ctx, ref_ascii, mlp, (drop, lo, hi), t_map, reads_cap=rc,
                        bases_cap=max(h.n_bases for h in hcs), pairs_cap=max(h.n_pairs for h in hcs),
                        ops_stride=64)
-    stats = {"miss": 0, "mapped": 0, "kept": 0, "trunc": 0, "mates": 0}
+    nd = len(hcs)
+    stats = {"miss_mapped": 0, "miss_all": 0, "mapped": 0, "kept": 0, "trunc": 0, "mates": 0}
 
     def consume(i, r):
-        best = plain_best[i % 2]
+        best = plain_best[i % nd]
         m = best >= t_map
         stats["mapped"] += int(m.sum())
-        stats["miss"] += int((r["best_score"][m] != best[m]).sum())
+        stats["miss_mapped"] += int((r["best_score"][m] != best[m]).sum())
+        stats["miss_all"] += int((r["best_score"] != best).sum())
         stats["kept"] += r["kept"]
         stats["trunc"] += int(np.count_nonzero(r["aln"]["status"] & 1))
         stats["mates"] += len(best)
 
-    st.run([hcs[0], hcs[1]])                      # warm-up
+    st.run(hcs[:2])                               # warm-up
     n_chunks = args.stream_chunks
+    order = [hcs[k % nd] for k in range(n_chunks)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    st.run([hcs[k % 2] for k in range(n_chunks)], consume)
+    st.run(order, consume)
     wall = time.perf_counter() - t1
     mates = stats["mates"]
-    pairs = sum(hcs[k % 2].n_pairs for k in range(n_chunks))
-    h2d = sum(hcs[k % 2].n_bases + 10 * hcs[k % 2].n_reads + 12 * hcs[k % 2].n_pairs
-              for k in range(n_chunks))
-    d2h = sum(hcs[k % 2].n_reads * (4 + 1 + 4 + 28 + 4 * 64) + 4 for k in range(n_chunks))
+    pairs = sum(h.n_pairs for h in order)
+    h2d = sum(h.n_bases + 10 * h.n_reads + 12 * h.n_pairs for h in order)
+    d2h = sum(h.n_reads * (4 + 1 + 4 + 28 + 4 * 64) + 4 for h in order)
     sw.sw_mlp_destroy(ctx, mlp)
     return {
         "workload": f"paired reads: {n_chunks} chunks of {args.stream_frags} fragments "
                     f"(insert 200-500 nt, 2 x 150-nt mates) from a 64 Mb reference, 16 windows of "
-                    f"200-1000 nt per mate; 2 distinct chunks generated and cycled",
+                    f"200-1000 nt per mate; {nd} distinct chunks generated and cycled",
         "chunks": n_chunks, "mates": mates, "fragments": mates // 2, "pairs": pairs,
         "wall_seconds": round(wall, 3),
         "mates_per_s": round(mates / wall, 1),
@@ -586,8 +770,12 @@ def bench_stream(ctx, args):
         "host_to_device_gb": round(h2d / 1e9, 3), "device_to_host_gb": round(d2h / 1e9, 3),
         "copy_gb_per_s_over_wall": round((h2d + d2h) / wall / 1e9, 2),
         "kept_pairs_fraction": round(stats["kept"] / pairs, 5),
-        "best_hit_recall_mapped_mates": round(1 - stats["miss"] / max(stats["mapped"], 1), 6),
-        "mapped_fraction": round(stats["mapped"] / mates, 5),
+        "best_hit_recall_mapped_mates": round(1 - stats["miss_mapped"] / max(stats["mapped"], 1), 6),
+        "best_hit_recall_all_mates": round(1 - stats["miss_all"] / max(mates, 1), 6),
+        "recall_note": "output-level rule: a mate predicted unmapped is not aligned, so over all "
+                       "mates (the strict reading) it counts as a miss unless plain SW has no "
+                       "alignment either; over mapped mates it is the output's recall",
+        "mapped_fraction": round(stats["mapped"] / max(mates, 1), 5),
         "cigar_truncated": stats["trunc"],
         "t_map": t_map, "thresholds": [drop, lo, hi],
         "includes": "host->device copies of reads and windows, encode, features, MLP, decision, "
@@ -595,8 +783,7 @@ def bench_stream(ctx, args):
         "setup_seconds": round(time.perf_counter() - t0 - wall, 1),
         "autotune": None if tune is None else [
             {"m_max": t["m_max"], "tile": [t["G"], t["RPL"]], "blocks_per_cu": t["blocks_per_cu"],
-             "path": PATHS.get(t["path"], "int32"), "ms": round(t["ms"], 3),
-             "ms_default": round(t["ms_default"], 3)} for t in tune],
+             "path": PATHS.get(t["path"], "int32"), "ms": round(t["ms"], 3)} for t in tune],
     }
 
 
@@ -624,8 +811,12 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(DESIGN.md describes how the work would shard).", file=sys.stderr)
+              "(the work would shard by whole reads; see the design notes).", file=sys.stderr)
         sys.exit(2)
+
+    # the stream's distinct chunks are generated by worker processes while the
+    # other sections run (started before this process touches the GPU)
+    gen = None if args.no_stream else start_stream_generation(args)
 
     import torch
 
@@ -745,16 +936,20 @@ def main():
                 ("k_sw_score16" if path == "int16x2" else "k_sw_score", tune_shape[0], tune_shape[1],
                  b.n_reads)),
             "kernel_ms": round(float(np.mean(score_ms)), 3),
-            "frac_of_int32_roofline": round(kern_gcups / PEAK_GCUPS_INT32, 4),
-            # the same instruction mixes with every instruction at 4 cycles
-            # (11 packed ops per 2 cells, 10 int32 ops per cell)
+            # the same datapath's instruction mix with every instruction at 4
+            # cycles (11 packed ops per 2 cells: 7,150 GCUPS; 10 int32 ops per
+            # cell: 3,932 GCUPS)
+            "peak_at_4_cycles_per_instruction": round(
+                (PEAK_GCUPS_INT16X2 * 42 / 44) if path == "int16x2" else (PEAK_GCUPS_INT32 * 32 / 40), 1),
             "frac_at_4_cycles_per_instruction": round(
                 kern_gcups / ((PEAK_GCUPS_INT16X2 * 42 / 44) if path == "int16x2"
                               else (PEAK_GCUPS_INT32 * 32 / 40)), 4),
-            "frac_of_int32_roofline_at_4_cycles_per_instruction": round(
-                kern_gcups / (PEAK_GCUPS_INT32 * 32 / 40), 4),
         },
     }
+    out["config1"] = bench_config1(ctx, args)
+    if not args.no_autotune:
+        log("autotune, mixed lengths ...")
+        out["autotune_mixed"] = bench_autotune_mixed(args)
     if tune is not None:
         out["autotune"] = [{"m_max": t["m_max"], "tile": [t["G"], t["RPL"]],
                             "blocks_per_cu": t["blocks_per_cu"], "path": PATHS.get(t["path"], "int32"),
@@ -770,11 +965,11 @@ def main():
         out["spliced"] = bench_spliced(ctx, args)
     if not args.no_stream:
         log("paired-read stream ...")
-        out["stream"] = bench_stream(ctx, args)
+        out["stream"] = bench_stream(ctx, args, gen)
     sw.sw_ctx_destroy(ctx)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds, c1=synth.config1())
     print(json.dumps(out), flush=True)
 
 
