@@ -493,3 +493,108 @@ def custom(ref: bytes, reads: list[bytes], windows: list[tuple]) -> Batch:
     rd = np.frombuffer(b"".join(reads), dtype=np.uint8).copy()
     return Batch(ref=np.frombuffer(ref, dtype=np.uint8).copy(), reads=rd, read_off=off,
                  read_len=lens, windows=win, truth={})
+
+
+def spliced_long(seed: int = BASE_SEED + 6, n_reads: int = 20_000, ref_len: int = 16_000_000,
+                 seed_len: int = 100, p_sub: float = 0.01) -> tuple:
+    """Spliced long reads with their seeds, for whole-read alignment over joined
+    windows and junction detection.
+
+    Each read is 2-4 exons of U[50, 300] nt with introns of U[50, 5000] nt,
+    rejection-sampled to 400-800 nt, from a gene on either reference strand: a
+    plus-strand gene's introns read GT...AG on the reference, a minus-strand
+    gene's CT...AC (the reverse complement of GT...AG).  The read is the exons'
+    reference sequence or, for half the reads, its reverse complement
+    (read strand 1), with substitutions at p_sub.  Seeds as in `spliced`: the
+    read cut into ceil(L/seed_len) seeds (last one right-aligned), each with
+    K ~ U{4..12} windows of U[200, 1000] nt on the read's strand, one covering
+    the seed's largest exonic part.
+
+    Returns (reads, seeds, truth): `reads` holds the long reads (no windows),
+    `seeds` the seed batch, and truth["seed_read"] the long read of every seed
+    (seeds of a read are contiguous), truth["junctions"] the planted introns as
+    rows (reference start, reference end exclusive, gene strand), and
+    truth["read_strand"], truth["exons"] (per read, list of (start, length))."""
+    g = rng(seed)
+    ref = make_reference(g, ref_len)
+    L = len(ref)
+    plans = []
+    for r in range(n_reads):
+        while True:
+            ne = int(g.integers(2, 5))
+            ex = g.integers(50, 301, size=ne)
+            if 400 <= ex.sum() <= 800:
+                break
+        intr = g.integers(50, 5001, size=ne - 1)
+        span = int(ex.sum() + intr.sum())
+        o = int(g.integers(8, L - span - 8))
+        gene_minus = bool(g.random() < 0.5)
+        starts = [o + int(ex[:e].sum() + intr[:e].sum()) for e in range(ne)]
+        plans.append((starts, ex, intr, gene_minus))
+    # motifs first, reads second: a later gene's motif may land in an earlier
+    # gene's exon (the read then carries it) or overwrite an earlier motif (that
+    # junction is then left out of the truth)
+    motif = {False: ((2, 3), (0, 2)), True: ((1, 3), (0, 1))}      # GT..AG / CT..AC
+    for starts, ex, intr, gm in plans:
+        for e in range(len(ex) - 1):
+            a = starts[e] + int(ex[e])
+            ref[a:a + 2] = motif[gm][0]
+            ref[a + int(intr[e]) - 2:a + int(intr[e])] = motif[gm][1]
+    reads, read_strand, exons_all, junctions = [], [], [], []
+    seeds, seed_read, seed_true = [], [], []
+    for r, (starts, ex, intr, gm) in enumerate(plans):
+        for e in range(len(ex) - 1):
+            a, b = starts[e] + int(ex[e]), starts[e] + int(ex[e]) + int(intr[e])
+            if (tuple(ref[a:a + 2]), tuple(ref[b - 2:b])) == motif[gm]:
+                junctions.append((a, b, 1 if gm else 0))
+        exons_all.append([(s, int(l)) for s, l in zip(starts, ex)])
+        seq = np.concatenate([ref[s:s + int(l)] for s, l in zip(starts, ex)]).copy()
+        seq_pos = np.concatenate([np.arange(s, s + int(l)) for s, l in zip(starts, ex)])
+        mut = g.random(len(seq)) < p_sub
+        seq[mut] = (seq[mut] + g.integers(1, 4, size=int(mut.sum()))) % 4
+        st = int(g.random() < 0.5)
+        read_strand.append(st)
+        reads.append((3 - seq[::-1]).astype(np.uint8) if st else seq)
+        Lr = len(seq)
+        for s in range(-(-Lr // seed_len)):
+            b = min(s * seed_len, Lr - seed_len)
+            part = seq[b:b + seed_len]
+            seeds.append((3 - part[::-1]).astype(np.uint8) if st else part.copy())
+            seed_read.append(r)
+            p = seq_pos[b:b + seed_len]
+            brk = np.nonzero(np.diff(p) != 1)[0]
+            bs = np.concatenate([[0], brk + 1])
+            be = np.concatenate([brk + 1, [len(p)]])
+            best = int(np.argmax(be - bs))
+            seed_true.append((int(p[bs[best]]), int(be[best] - bs[best]), int(p[0]), int(p[-1]), st))
+    ns = len(seeds)
+    k = g.integers(4, 13, size=ns)
+    P = int(k.sum())
+    win = np.zeros(P, dtype=WINDOW_DTYPE)
+    win["read_id"] = np.repeat(np.arange(ns, dtype=np.uint32), k)
+    wl = g.integers(200, 1001, size=P)
+    win["len"] = wl
+    win["ref_begin"] = g.integers(0, L - wl + 1)
+    st_seed = np.array([t[4] for t in seed_true], dtype=np.uint8)
+    win["strand"] = np.repeat(st_seed, k)
+    first = np.concatenate([[0], np.cumsum(k[:-1])])
+    slot = (g.random(ns) * k).astype(np.int64)
+    for s in range(ns):
+        p = int(first[s] + slot[s])
+        w = int(wl[p])
+        lo_pos, span_len, p0, p1, _ = seed_true[s]
+        if p1 - p0 + 1 <= w:
+            lo, ln = p0, p1 - p0 + 1
+        else:
+            lo, ln = lo_pos, span_len
+        a = max(0, lo + ln - w)
+        bmax = min(lo, L - w)
+        win["ref_begin"][p] = int(g.integers(a, max(a, bmax) + 1))
+        win["flags"][p] = FLAG_TRUE_ORIGIN
+    rs = np.array(read_strand, dtype=np.uint8)
+    seed_b = _assemble_fixed(ref, np.stack(seeds).astype(np.uint8), win,
+                             dict(seed_read=np.array(seed_read, dtype=np.uint32)))
+    long_b = assemble(ref, reads, np.zeros(0, dtype=WINDOW_DTYPE), {})
+    truth = dict(seed_read=np.array(seed_read, dtype=np.uint32), read_strand=rs,
+                 junctions=np.array(junctions, dtype=np.int64).reshape(-1, 3), exons=exons_all)
+    return long_b, seed_b, truth

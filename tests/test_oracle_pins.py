@@ -12,7 +12,8 @@ from oracle import brute
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_examples.txt")
 DEF = (5, -4, -10, -1)
-SCHEMES = [DEF, (2, -3, -4, -4), (3, -1, -5, -2), (1, 0, -2, -1), (4, -6, -7, -3)]
+SCHEMES = [DEF, (2, -3, -4, -4), (3, -1, -5, -2), (1, 0, -2, -1), (4, -6, -7, -3),
+           (5, -4, -20, 0), (2, -3, -4, 0)]    # the last two: length-free gaps
 
 
 def _cig(orc, ops):
