@@ -205,6 +205,108 @@ sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *batch, const sw_scorin
                              uint32_t *d_ops, uint32_t ops_stride, const sw_hit *d_hits,
                              void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Spliced reads (Sec. 2, "Stage E: SWA + Splice Junctions", tasks i, ii, iv).
+ *
+ * A long read is cut into seeds; every seed is aligned against its candidate
+ * windows (sw_batch_score, sw_best_per_read, sw_batch_traceback).  The
+ * reference span of a seed's best alignment is a candidate alignment location
+ * (CAL) of the read.  Each CAL is extended on both sides (task i, 30 bases by
+ * default) and the extended CALs of a read that lie closer than the longest
+ * intron are joined into one window (task ii); the whole read is aligned
+ * against its joined windows (task iii, the calls above, with a scoring whose
+ * gap extension is 0 so that an intron costs one gap open), and a long run of
+ * deletions whose ends carry an intron motif becomes a splice junction
+ * (task iv), counted in a table that lives across batches (the paper's AVL
+ * tree; here a device hash table).
+ * ------------------------------------------------------------------------- */
+
+/* One CAL: reference bases [first, last] (absolute, inclusive) of read read_id
+ * on strand `strand` (1: the read's reverse complement aligns there); valid 0
+ * marks a seed without a CAL.  16 bytes. */
+typedef struct {
+    uint32_t read_id;
+    uint32_t first, last;
+    uint8_t strand;
+    uint8_t valid;
+    uint16_t reserved;   /* written as 0 */
+} sw_cal;
+
+/* One splice junction: intron [start, end) in absolute reference positions;
+ * strand 0: the intron reads GT...AG on the reference (a gene on the forward
+ * strand), 1: CT...AC (a gene on the reverse strand); count: the alignments
+ * that reported it.  24 bytes. */
+typedef struct {
+    uint64_t start, end;
+    uint32_t count;
+    uint32_t strand;
+} sw_junction;
+
+/* CALs of n_seeds seeds: seed s belongs to long read d_seed_read[s], its best
+ * window is d_best_pair[s] (a pair of `seeds`, from sw_best_per_read) and
+ * d_aln[s] its alignment there (sw_batch_traceback with those pair ids).
+ * d_cals[s] = {d_seed_read[s], window start + aln.ref_begin, window start +
+ * aln.ref_end, window strand, 1} when the pair exists, the alignment scores at
+ * least max(min_score, 1) and its last base lies below 2^32; otherwise
+ * {d_seed_read[s], 0, 0, 0, 0}.  All arrays are device arrays of n_seeds. */
+sw_status sw_seed_cals(sw_ctx *ctx, const sw_batch *seeds, const uint32_t *d_best_pair,
+                       const sw_aln *d_aln, const uint32_t *d_seed_read, uint32_t n_seeds,
+                       int32_t min_score, sw_cal *d_cals, void *stream);
+
+/* Joined windows from n_cals CALs, which must be grouped by read (non-decreasing
+ * read ids: a read whose CALs form several separate runs has each run joined
+ * on its own; the call cannot check the order without a host round trip).
+ * Per read, the first 16 valid CALs with first <= last < ref_len count; CALs
+ * of reads >= n_reads are ignored.  Each becomes [max(first - ext, 0),
+ * min(last + ext, ref_len - 1)]; sorted by (strand, first, last), a CAL joins
+ * the current window when it has the window's strand and fewer than max_gap
+ * bases lie strictly between the window's end and its first base (overlap
+ * joins); the window's end becomes the larger of the two.  Windows are
+ * written to d_win_out (capacity n_cals, never exceeded) read by read in that
+ * order, as {read, first, min(length, 65535), strand, flags 0}, and their
+ * number to *d_n_out (device), ready for a batch with d_n_pairs = d_n_out.
+ * Uses context scratch (about 17 bytes per CAL; growing it fails with
+ * SW_E_STATE under capture or while a captured graph is alive). */
+sw_status sw_join_cals(sw_ctx *ctx, const sw_cal *d_cals, uint32_t n_cals, uint32_t n_reads,
+                       uint64_t ref_len, uint32_t ext, uint32_t max_gap, sw_window *d_win_out,
+                       uint32_t *d_n_out, void *stream);
+
+/* Junction table: caller-owned device arrays d_keys[capacity] (uint64) and
+ * d_counts[capacity] (uint32), capacity a power of two in [1, 2^31].  Zero
+ * them with sw_junctions_clear before first use; sw_detect_junctions adds to
+ * them, so a table accumulates over any number of batches.  An entry is key
+ * (start << 17 | length << 1 | strand, 0 = empty) and its count. */
+sw_status sw_junctions_clear(sw_ctx *ctx, uint64_t *d_keys, uint32_t *d_counts,
+                             uint32_t capacity, void *stream);
+
+/* Junction search on n alignments of `batch`: alignment k is d_aln[k] with ops
+ * d_ops[k * ops_stride ...] for pair d_pair_ids[k] (the arguments of the
+ * sw_batch_traceback call that produced them).  Alignments with status bits
+ * set, score < max(min_score, 1), or a pair outside the batch are left alone.
+ * In the others, every deletion run of L >= min_intron bases (min_intron >= 4)
+ * whose neighbours are match runs of a and b bases may move by s,
+ * -(a-1) <= s <= b-1, where each step keeps the score (a step left needs the
+ * reference base before the run to equal the run's last base, a step right the
+ * run's first base to equal the base after it); the leftmost reachable
+ * placement whose run starts with GT and ends with AG (strand 0) or starts with
+ * CT and ends with AC (strand 1) is a junction: the run is rewritten in place
+ * as an N op (its neighbours as a + s and b - s matches, so the score is
+ * unchanged) and the junction's count in the table goes up by one.  Runs
+ * without such a placement stay deletions.  d_n_junc (device, may be NULL)
+ * receives the junctions found per alignment; *d_dropped (device, may be
+ * NULL) is incremented once per junction the full table could not take. */
+sw_status sw_detect_junctions(sw_ctx *ctx, const sw_batch *batch, const uint32_t *d_pair_ids,
+                              uint32_t n, const sw_aln *d_aln, uint32_t *d_ops,
+                              uint32_t ops_stride, int32_t min_score, uint32_t min_intron,
+                              uint64_t *d_keys, uint32_t *d_counts, uint32_t capacity,
+                              uint32_t *d_n_junc, uint32_t *d_dropped, void *stream);
+
+/* The table's junctions, in no particular order: the first out_cap go to
+ * d_out, and their total number to *d_n (device; may exceed out_cap). */
+sw_status sw_list_junctions(sw_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_counts,
+                            uint32_t capacity, sw_junction *d_out, uint32_t out_cap,
+                            uint32_t *d_n, void *stream);
+
 /* Graph capture (the orchestration of a batch without per-call launch cost).
  * Every library call issued on `stream` between sw_graph_begin and
  * sw_graph_end is recorded, not run; sw_graph_launch replays the recording on

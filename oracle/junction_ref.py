@@ -11,11 +11,14 @@ or CT...AC for a gene on the other strand (task iv).  Junctions are counted
 over all reads (the paper keeps the counts in an AVL tree).  This module is
 the plain definition of those steps:
 
-CALs.  A CAL is (read, first reference base, last reference base, strand),
-absolute inclusive coordinates.  Here a read's CALs are the reference spans of
-its seeds' best local alignments scoring at least a threshold.
+CALs.  A CAL is (read, first reference base, last reference base, strand,
+valid), absolute inclusive coordinates.  Here a read's CALs are the reference
+spans of its seeds' best local alignments scoring at least a threshold
+(positions are 32-bit, like a window's start: a span reaching 2^32 is not a
+CAL).
 
-Joining (per read, at most MAX_CALS CALs, the first ones in input order).
+Joining (per read, at most MAX_CALS CALs: the first valid ones in input order
+with first <= last < ref_len).
 Each CAL [b, e] becomes [max(b - ext, 0), min(e + ext, ref_len - 1)].  The
 extended CALs are sorted by (strand, first base, last base); walking that
 order, a CAL joins the current window when it has the window's strand and the
@@ -63,6 +66,8 @@ def seed_cals(windows, best_pair, aln, seed_read, min_score):
             w = windows[p]
             b = int(w["ref_begin"]) + int(a["ref_begin"])
             e = int(w["ref_begin"]) + int(a["ref_end"])
+            ok = e < 2 ** 32
+        if ok:
             out.append((int(seed_read[s]), b, e, int(w["strand"]), 1))
         else:
             out.append((int(seed_read[s]), 0, 0, 0, 0))
@@ -74,7 +79,7 @@ def join_cals(cals, n_reads, ref_len, ext=EXT, max_gap=5000):
     by_read = [[] for _ in range(n_reads)]
     for c in cals:
         r = c[0]
-        if r < n_reads and c[4] and len(by_read[r]) < MAX_CALS:
+        if r < n_reads and c[4] and c[1] <= c[2] < ref_len and len(by_read[r]) < MAX_CALS:
             by_read[r].append(c)
     out = []
     for r in range(n_reads):

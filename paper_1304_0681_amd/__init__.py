@@ -31,6 +31,10 @@ ALN_DTYPE = np.dtype([("score", "<i4"), ("read_begin", "<i4"), ("read_end", "<i4
                       ("status", "<u4")])
 WINDOW_DTYPE = np.dtype([("read_id", "<u4"), ("ref_begin", "<u4"), ("len", "<u2"),
                          ("strand", "u1"), ("flags", "u1")])
+CAL_DTYPE = np.dtype([("read_id", "<u4"), ("first", "<u4"), ("last", "<u4"), ("strand", "u1"),
+                      ("valid", "u1"), ("reserved", "<u2")])
+JUNCTION_DTYPE = np.dtype([("start", "<u8"), ("end", "<u8"), ("count", "<u4"),
+                           ("strand", "<u4")])
 
 
 class SwError(RuntimeError):
@@ -113,6 +117,12 @@ def lib() -> ctypes.CDLL:
         L.sw_autotune_cached.argtypes = [P, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scoring),
                                          U32, ctypes.c_int, ctypes.c_char_p,
                                          ctypes.POINTER(ctypes.c_int), P, P]
+        L.sw_seed_cals.argtypes = [P, ctypes.POINTER(sw_batch), P, P, P, U32, I32, P, P]
+        L.sw_join_cals.argtypes = [P, P, U32, U32, U64, U32, U32, P, P, P]
+        L.sw_junctions_clear.argtypes = [P, P, P, U32, P]
+        L.sw_detect_junctions.argtypes = [P, ctypes.POINTER(sw_batch), P, U32, P, P, U32, I32,
+                                          U32, P, P, U32, P, P, P]
+        L.sw_list_junctions.argtypes = [P, P, P, U32, P, U32, P, P]
         L.sw_graph_begin.argtypes = [P, P]
         L.sw_graph_end.argtypes = [P, P, ctypes.POINTER(P)]
         L.sw_graph_launch.argtypes = [P, P, P]
@@ -126,7 +136,8 @@ def lib() -> ctypes.CDLL:
                   "sw_mlp_destroy", "sw_mlp_set_params", "sw_mlp_get_params", "sw_features",
                   "sw_mlp_save", "sw_mlp_load",
                   "sw_mlp_forward", "sw_mlp_grad", "sw_mlp_train_step", "sw_mlp_labels",
-                  "sw_filter_candidates"):
+                  "sw_filter_candidates", "sw_seed_cals", "sw_join_cals", "sw_junctions_clear",
+                  "sw_detect_junctions", "sw_list_junctions"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -315,6 +326,40 @@ def sw_autotune_cached(ctx, batch, scoring, cache_path, flags=0, repeats=3, stre
     return [{f: getattr(e, f) for f, _ in sw_tune_entry._fields_} for e in out], bool(hit.value)
 
 
+def sw_seed_cals(ctx, batch, d_best_pair, d_aln, d_seed_read, n_seeds, min_score, d_cals,
+                 stream=None):
+    _check(ctx, lib().sw_seed_cals(ctx, ctypes.byref(batch.c), _ptr(d_best_pair), _ptr(d_aln),
+                                   _ptr(d_seed_read), int(n_seeds), int(min_score), _ptr(d_cals),
+                                   _stream_ptr(stream)))
+
+
+def sw_join_cals(ctx, d_cals, n_cals, n_reads, ref_len, ext, max_gap, d_win_out, d_n_out,
+                 stream=None):
+    _check(ctx, lib().sw_join_cals(ctx, _ptr(d_cals), int(n_cals), int(n_reads), int(ref_len),
+                                   int(ext), int(max_gap), _ptr(d_win_out), _ptr(d_n_out),
+                                   _stream_ptr(stream)))
+
+
+def sw_junctions_clear(ctx, d_keys, d_counts, capacity, stream=None):
+    _check(ctx, lib().sw_junctions_clear(ctx, _ptr(d_keys), _ptr(d_counts), int(capacity),
+                                         _stream_ptr(stream)))
+
+
+def sw_detect_junctions(ctx, batch, d_pair_ids, n, d_aln, d_ops, ops_stride, min_score,
+                        min_intron, d_keys, d_counts, capacity, d_n_junc=None, d_dropped=None,
+                        stream=None):
+    _check(ctx, lib().sw_detect_junctions(ctx, ctypes.byref(batch.c), _ptr(d_pair_ids), int(n),
+                                          _ptr(d_aln), _ptr(d_ops), int(ops_stride),
+                                          int(min_score), int(min_intron), _ptr(d_keys),
+                                          _ptr(d_counts), int(capacity), _ptr(d_n_junc),
+                                          _ptr(d_dropped), _stream_ptr(stream)))
+
+
+def sw_list_junctions(ctx, d_keys, d_counts, capacity, d_out, out_cap, d_n, stream=None):
+    _check(ctx, lib().sw_list_junctions(ctx, _ptr(d_keys), _ptr(d_counts), int(capacity),
+                                        _ptr(d_out), int(out_cap), _ptr(d_n), _stream_ptr(stream)))
+
+
 def sw_graph_begin(ctx, stream):
     """Start recording the library calls issued on `stream` (a torch.cuda.Stream
     created by the caller, not the null stream)."""
@@ -417,3 +462,7 @@ def hits_to_numpy(t) -> np.ndarray:
 
 def aln_to_numpy(t) -> np.ndarray:
     return t.cpu().numpy().view(ALN_DTYPE).reshape(-1)
+
+
+def junctions_to_numpy(t) -> np.ndarray:
+    return t.cpu().numpy().view(JUNCTION_DTYPE).reshape(-1)

@@ -57,6 +57,9 @@ struct sw_ctx {
     // filter scratch: read segments (first, last, count) and compaction offsets
     uint32_t *seg = nullptr;
     size_t seg_bytes = 0;
+    // CAL joining scratch: windows, flags, compaction ids and scan words
+    void *join = nullptr;
+    size_t join_bytes = 0;
     ClassShape shapes[kNumClasses];
     int blocks_per_cu[kNumClasses];
     ClassEdges edges;    // query-length class bounds of the score path
@@ -282,6 +285,7 @@ sw_status sw_ctx_destroy(sw_ctx *ctx)
     if (ctx->keys) keep(hipFree(ctx->keys));
     if (ctx->tb) keep(hipFree(ctx->tb));
     if (ctx->seg) keep(hipFree(ctx->seg));
+    if (ctx->join) keep(hipFree(ctx->join));
     for (auto &ev : ctx->ev)
         if (ev) keep(hipEventDestroy(ev));
     delete ctx;
@@ -1481,6 +1485,138 @@ int sw_cigar_string(const uint32_t *ops, uint32_t n_ops, char *buf, uint32_t cap
     }
     buf[k] = 0;
     return (int)k;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Spliced reads: CALs, joined windows, junctions.
+// ---------------------------------------------------------------------------
+extern "C" {
+
+sw_status sw_seed_cals(sw_ctx *ctx, const sw_batch *seeds, const uint32_t *d_best_pair,
+                       const sw_aln *d_aln, const uint32_t *d_seed_read, uint32_t n_seeds,
+                       int32_t min_score, sw_cal *d_cals, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    sw_status st = check_batch(ctx, seeds);
+    if (st)
+        return st;
+    if (n_seeds == 0)
+        return SW_OK;
+    if (!d_best_pair || !d_aln || !d_seed_read || !d_cals)
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    if (seeds->n_pairs && !seeds->d_win)
+        return fail(ctx, SW_E_INVALID, "batch has no windows");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_seed_cals(*seeds, d_best_pair, d_aln, d_seed_read, n_seeds, min_score,
+                                  d_cals, static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_join_cals(sw_ctx *ctx, const sw_cal *d_cals, uint32_t n_cals, uint32_t n_reads,
+                       uint64_t ref_len, uint32_t ext, uint32_t max_gap, sw_window *d_win_out,
+                       uint32_t *d_n_out, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    if (!d_n_out || (n_cals && (!d_cals || !d_win_out)))
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    if (ref_len >= (1ull << 36))
+        return fail(ctx, SW_E_RANGE, "reference longer than 2^36 bases");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const size_t n = std::max<uint32_t>(n_cals, 1);
+    const size_t o_keep = align_up(sizeof(sw_window) * n);
+    const size_t o_ids = o_keep + align_up(n);
+    const size_t o_scan = o_ids + align_up(4 * n);
+    const size_t need = o_scan + align_up(4 * compact_scratch_words(n_cals));
+    void *buf = ctx->join;
+    size_t have = ctx->join_bytes;
+    sw_status st = ensure(ctx, &buf, &have, need);
+    if (st)
+        return st;
+    ctx->join = buf;
+    ctx->join_bytes = have;
+    char *p = static_cast<char *>(buf);
+    sw_window *tmp = reinterpret_cast<sw_window *>(p);
+    uint8_t *keep = reinterpret_cast<uint8_t *>(p + o_keep);
+    uint32_t *ids = reinterpret_cast<uint32_t *>(p + o_ids);
+    uint32_t *scan = reinterpret_cast<uint32_t *>(p + o_scan);
+    if (n_cals && ref_len)
+        HIP_TRY(ctx, launch_join(n_cals, d_cals, n_reads, ref_len, ext, max_gap, tmp, keep, s));
+    // no CAL can be valid without a reference: the compaction of nothing
+    // writes the zero count
+    HIP_TRY(ctx, compact_pairs(ref_len ? n_cals : 0, keep, tmp, d_win_out, ids, d_n_out, scan, s));
+    return SW_OK;
+}
+
+static sw_status check_table(sw_ctx *ctx, const void *keys, const void *counts, uint32_t cap)
+{
+    if (!keys || !counts)
+        return fail(ctx, SW_E_INVALID, "NULL table");
+    if (cap == 0 || (cap & (cap - 1)) || cap > (1u << 31))
+        return fail(ctx, SW_E_INVALID, "table capacity %u is not a power of two in [1, 2^31]", cap);
+    return SW_OK;
+}
+
+sw_status sw_junctions_clear(sw_ctx *ctx, uint64_t *d_keys, uint32_t *d_counts, uint32_t capacity,
+                             void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    sw_status st = check_table(ctx, d_keys, d_counts, capacity);
+    if (st)
+        return st;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_table_clear(d_keys, d_counts, capacity, static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_detect_junctions(sw_ctx *ctx, const sw_batch *b, const uint32_t *d_pair_ids,
+                              uint32_t n, const sw_aln *d_aln, uint32_t *d_ops,
+                              uint32_t ops_stride, int32_t min_score, uint32_t min_intron,
+                              uint64_t *d_keys, uint32_t *d_counts, uint32_t capacity,
+                              uint32_t *d_n_junc, uint32_t *d_dropped, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    sw_status st = check_batch(ctx, b);
+    if (st)
+        return st;
+    if ((st = check_table(ctx, d_keys, d_counts, capacity)))
+        return st;
+    if (min_intron < 4)
+        return fail(ctx, SW_E_INVALID, "min_intron must be at least 4 (GT + AG)");
+    if (n == 0)
+        return SW_OK;
+    if (!d_pair_ids || !d_aln || (!d_ops && ops_stride))
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    if (b->n_pairs == 0)
+        return fail(ctx, SW_E_INVALID, "alignments given for an empty batch");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_detect(*b, d_pair_ids, n, d_aln, d_ops, ops_stride, min_score, min_intron,
+                               d_keys, d_counts, capacity, d_n_junc, d_dropped,
+                               static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_list_junctions(sw_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_counts,
+                            uint32_t capacity, sw_junction *d_out, uint32_t out_cap, uint32_t *d_n,
+                            void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    sw_status st = check_table(ctx, d_keys, d_counts, capacity);
+    if (st)
+        return st;
+    if (!d_n || (out_cap && !d_out))
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_list(d_keys, d_counts, capacity, d_out, out_cap, d_n,
+                             static_cast<hipStream_t>(stream)));
+    return SW_OK;
 }
 
 }  // extern "C"

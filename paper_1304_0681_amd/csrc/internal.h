@@ -127,4 +127,20 @@ hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &
                                   const uint32_t *maxlen, const TbBand &band, int grid,
                                   hipStream_t st);
 
+// Spliced reads (splice.hip).
+hipError_t launch_seed_cals(const sw_batch &b, const uint32_t *best_pair, const sw_aln *aln,
+                            const uint32_t *seed_read, uint32_t n_seeds, int32_t min_score,
+                            sw_cal *out, hipStream_t st);
+// Joined windows of each run at the run's own positions of tmp, flagged in keep.
+hipError_t launch_join(uint32_t n, const sw_cal *cals, uint32_t n_reads, uint64_t ref_len,
+                       uint32_t ext, uint32_t max_gap, sw_window *tmp, uint8_t *keep,
+                       hipStream_t st);
+hipError_t launch_detect(const sw_batch &b, const uint32_t *pair_ids, uint32_t n, const sw_aln *aln,
+                         uint32_t *ops, uint32_t ops_stride, int32_t min_score, uint32_t min_intron,
+                         uint64_t *keys, uint32_t *counts, uint32_t cap, uint32_t *n_junc,
+                         uint32_t *dropped, hipStream_t st);
+hipError_t launch_table_clear(uint64_t *keys, uint32_t *counts, uint32_t cap, hipStream_t st);
+hipError_t launch_list(const uint64_t *keys, const uint32_t *counts, uint32_t cap, sw_junction *out,
+                       uint32_t out_cap, uint32_t *d_n, hipStream_t st);
+
 }  // namespace hpgsw

@@ -1,8 +1,8 @@
-// Host stand-in for the few HIP runtime declarations the score kernels' source
-// uses, so that the unmodified kernel file compiles as plain C++ for the CPU
-// model of a wave (tests/host_model/score_model.cpp).  Kernel launches compile
-// to nothing; the model calls the kernel functions itself, one thread per
-// lane.  Cross-lane operations and the AMDGPU builtins the kernels use are
+// Host stand-in for the few HIP runtime declarations the score and splice
+// kernels' sources use, so that the unmodified kernel files compile as plain
+// C++ for the CPU models (tests/host_model/score_model.cpp and
+// splice_model.cpp).  Kernel launches compile to nothing; the models call the
+// kernel functions themselves, one thread (or one loop step) per lane.  Cross-lane operations and the AMDGPU builtins the kernels use are
 // declared here and defined by the model.
 #pragma once
 
@@ -33,19 +33,21 @@ inline int2 make_int2(int x, int y) { return int2{x, y}; }
 struct ModelIdx {
     unsigned x, y, z;
 };
-extern thread_local ModelIdx threadIdx, blockIdx;
+extern thread_local ModelIdx threadIdx, blockIdx, gridDim;
 
 inline int max(int a, int b) { return a > b ? a : b; }
 inline int min(int a, int b) { return a < b ? a : b; }
 inline unsigned max(unsigned a, unsigned b) { return a > b ? a : b; }
 inline unsigned min(unsigned a, unsigned b) { return a < b ? a : b; }
 inline uint64_t min(uint64_t a, uint64_t b) { return a < b ? a : b; }
+inline uint64_t max(uint64_t a, uint64_t b) { return a > b ? a : b; }
 
 int model_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl);
 int __shfl(int v, int src, int width = 64);
 int __shfl_xor(int v, int mask, int width = 64);
 uint64_t __shfl_xor(uint64_t v, int mask, int width = 64);
 uint32_t atomicAdd(uint32_t *p, uint32_t v);
+unsigned long long atomicCAS(unsigned long long *p, unsigned long long cmp, unsigned long long v);
 uint32_t model_perm(uint32_t hi, uint32_t lo, uint32_t sel);
 uint32_t model_alignbit(uint32_t hi, uint32_t lo, uint32_t shift);
 int model_sbfe(int src, int offset, int width);

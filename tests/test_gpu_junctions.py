@@ -1,0 +1,293 @@
+"""Spliced reads on the GPU: CALs from seed alignments, joined windows, junction
+detection and counting, each bit-exact against the oracle
+(oracle/junction_ref.py) on the seeded inputs of tests/splice_inputs.py, and
+the whole spliced pass (seeds -> CALs -> joined windows -> whole-read
+alignment -> junctions) on spliced long reads against the oracle's chain."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1304_0681_amd as sw
+import synth
+from oracle import junction_ref as jr
+from paper_1304_0681_amd.splice import LONG_SCORING, SEED_SCORING, SplicedPass
+from splice_inputs import ALN_DTYPE, CAL_DTYPE, WINDOW_DTYPE, planted_alignments, random_cals
+
+pytestmark = pytest.mark.gpu
+
+MIN_INTRON = 40
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch.cuda.set_device(0)
+    c = sw.sw_ctx_create(0)
+    yield c
+    sw.sw_ctx_destroy(c)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.uint8).copy()).cuda()
+
+
+def _cal_tuples(c):
+    return [(int(x["read_id"]), int(x["first"]), int(x["last"]), int(x["strand"]), int(x["valid"]))
+            for x in c]
+
+
+def _batch_for(ctx, ref_codes, windows, n_reads):
+    """A device batch over `ref_codes` with `windows` and n_reads one-base reads
+    (the calls tested here read the windows and the reference only)."""
+    reads = [b"A"] * n_reads
+    b = synth.custom(synth.ASCII[ref_codes].tobytes(), reads, [])
+    return sw.DeviceBatch(ctx, b.ref, b.reads, b.read_off, b.read_len, windows)
+
+
+def test_seed_cals(ctx):
+    g = np.random.default_rng(31)
+    n_pairs, n_seeds = 900, 700
+    ref = g.integers(0, 4, 200_000).astype(np.uint8)
+    win = np.zeros(n_pairs, WINDOW_DTYPE)
+    win["read_id"] = g.integers(0, n_seeds, n_pairs)
+    win["ref_begin"] = g.integers(0, 199_000, n_pairs)
+    win["len"] = g.integers(1, 1000, n_pairs)
+    win["strand"] = g.integers(0, 2, n_pairs)
+    best = g.integers(0, n_pairs + 50, n_seeds).astype(np.uint32)
+    best[:5] = 0xFFFFFFFF
+    aln = np.zeros(n_seeds, ALN_DTYPE)
+    aln["score"] = g.integers(-1, 300, n_seeds)
+    aln["ref_begin"] = g.integers(0, 500, n_seeds)
+    aln["ref_end"] = aln["ref_begin"] + g.integers(0, 400, n_seeds)
+    neg = aln["score"] <= 0
+    aln["ref_begin"][neg] = -1
+    aln["ref_end"][neg] = -1
+    seed_read = np.sort(g.integers(0, 150, n_seeds)).astype(np.uint32)
+    db = _batch_for(ctx, ref, win, n_seeds)
+    out = torch.empty(n_seeds * 16, dtype=torch.uint8, device="cuda")
+    sw.sw_seed_cals(ctx, db, _dev(best), _dev(aln), _dev(seed_read), n_seeds, 60, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(CAL_DTYPE)
+    assert _cal_tuples(got) == jr.seed_cals(win, best, aln, seed_read, 60)
+    assert 100 < int(got["valid"].sum()) < n_seeds
+
+
+@pytest.mark.parametrize("ext,max_gap", [(30, 5000), (0, 1), (100, 0)])
+def test_join(ctx, ext, max_gap):
+    ref_len, n_reads = 3_000_000, 3000
+    cals = random_cals(40 + ext, n_reads, ref_len, ext, max_gap)
+    n = len(cals)
+    out = torch.empty(n * 12, dtype=torch.uint8, device="cuda")
+    n_out = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    sw.sw_join_cals(ctx, _dev(cals), n, n_reads, ref_len, ext, max_gap, out, n_out)
+    torch.cuda.synchronize()
+    k = int(n_out.item())
+    w = out.cpu().numpy().view(WINDOW_DTYPE)[:k]
+    got = [(int(x["read_id"]), int(x["ref_begin"]), int(x["len"]), int(x["strand"])) for x in w]
+    ref = jr.join_cals(_cal_tuples(cals), n_reads, ref_len, ext=ext, max_gap=max_gap)
+    assert got == ref
+    assert (w["flags"] == 0).all() and k > 1500
+
+
+def test_join_edge_cases(ctx):
+    n_out = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    out = torch.empty(64 * 12, dtype=torch.uint8, device="cuda")
+    # no CALs at all
+    sw.sw_join_cals(ctx, None, 0, 10, 1000, 30, 100, None, n_out)
+    torch.cuda.synchronize()
+    assert int(n_out.item()) == 0
+    # only invalid CALs, and one read with a single CAL at both reference ends
+    c = np.zeros(6, CAL_DTYPE)
+    c["read_id"] = [0, 0, 1, 2, 2, 5]
+    c["first"] = [10, 50, 0, 990, 995, 3]
+    c["last"] = [20, 40, 5, 999, 999, 4]
+    c["valid"] = [0, 1, 1, 1, 1, 1]         # (0, 50..40) has first > last; read 5 >= n_reads
+    n_out.fill_(-1)
+    sw.sw_join_cals(ctx, _dev(c), 6, 3, 1000, 30, 100, out, n_out)
+    torch.cuda.synchronize()
+    k = int(n_out.item())
+    w = out.cpu().numpy().view(WINDOW_DTYPE)[:k]
+    got = [(int(x["read_id"]), int(x["ref_begin"]), int(x["len"]), int(x["strand"])) for x in w]
+    assert got == jr.join_cals(_cal_tuples(c), 3, 1000, ext=30, max_gap=100) == \
+        [(1, 0, 36, 0), (2, 960, 40, 0)]
+
+
+def _oracle_detect(ref, win, aln, ops, min_score, ids=None):
+    want_ops, want_nj, lists = ops.copy(), [], []
+    for k in range(len(aln)):
+        a = aln[k]
+        p = k if ids is None else int(ids[k])
+        if a["status"] or a["score"] < max(min_score, 1) or p >= len(win):
+            want_nj.append(0)
+            continue
+        w = win[p]
+        t = ref[int(w["ref_begin"]):int(w["ref_begin"]) + int(w["len"])]
+        n = int(a["n_ops"])
+        new, js = jr.detect(t, ops[k, :n], int(a["ref_begin"]), MIN_INTRON, int(w["ref_begin"]))
+        want_ops[k, :n] = new
+        want_nj.append(len(js))
+        lists.append(js)
+    return want_ops, np.array(want_nj), jr.count(lists)
+
+
+def _listed(ctx, keys, counts, cap):
+    out = torch.empty(cap * 24, dtype=torch.uint8, device="cuda")
+    n = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sw.sw_list_junctions(ctx, keys, counts, cap, out, cap, n)
+    torch.cuda.synchronize()
+    j = sw.junctions_to_numpy(out)[:int(n.item())]
+    return {(int(r["start"]), int(r["end"]), int(r["strand"])): int(r["count"]) for r in j}
+
+
+def test_detect_count_accumulate(ctx):
+    n_aln, stride, cap = 4000, 48, 1 << 14
+    ref, win, aln, ops = planted_alignments(51, n_aln, MIN_INTRON, stride, 30)
+    db = _batch_for(ctx, ref, win, n_aln)
+    d_ops = _dev(ops)
+    keys = torch.empty(cap, dtype=torch.int64, device="cuda")
+    counts = torch.empty(cap, dtype=torch.int32, device="cuda")
+    nj = torch.empty(n_aln, dtype=torch.int32, device="cuda")
+    dropped = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ids = _dev(np.arange(n_aln, dtype=np.uint32))
+    sw.sw_junctions_clear(ctx, keys, counts, cap)
+    sw.sw_detect_junctions(ctx, db, ids, n_aln, _dev(aln), d_ops, stride, 30, MIN_INTRON, keys,
+                           counts, cap, nj, dropped)
+    torch.cuda.synchronize()
+    want_ops, want_nj, want = _oracle_detect(ref, win, aln, ops, 30)
+    assert (d_ops.cpu().numpy().view(np.uint32).reshape(n_aln, stride) == want_ops).all()
+    assert (nj.cpu().numpy() == want_nj).all()
+    assert int(dropped.item()) == 0
+    assert _listed(ctx, keys, counts, cap) == dict(want)
+    assert sum(want.values()) > 2000 and {s for _, _, s in want} == {0, 1}
+    # the same alignments again (from their original ops) double every count
+    sw.sw_detect_junctions(ctx, db, ids, n_aln, _dev(aln), _dev(ops), stride, 30, MIN_INTRON,
+                           keys, counts, cap, None, None)
+    torch.cuda.synchronize()
+    assert _listed(ctx, keys, counts, cap) == {k: 2 * v for k, v in want.items()}
+    # a table too small: what fits is exact, the rest is counted as dropped
+    small = 64
+    ks = torch.empty(small, dtype=torch.int64, device="cuda")
+    cs = torch.empty(small, dtype=torch.int32, device="cuda")
+    sw.sw_junctions_clear(ctx, ks, cs, small)
+    dropped.zero_()
+    sw.sw_detect_junctions(ctx, db, ids, n_aln, _dev(aln), _dev(ops), stride, 30, MIN_INTRON, ks,
+                           cs, small, None, dropped)
+    torch.cuda.synchronize()
+    tab = _listed(ctx, ks, cs, small)
+    assert len(tab) == small and all(want[k] == v for k, v in tab.items())
+    assert int(dropped.item()) == sum(want.values()) - sum(tab.values())
+
+
+def test_detect_argument_errors(ctx):
+    ref, win, aln, ops = planted_alignments(52, 4, MIN_INTRON)
+    db = _batch_for(ctx, ref, win, 4)
+    keys = torch.zeros(8, dtype=torch.int64, device="cuda")
+    counts = torch.zeros(8, dtype=torch.int32, device="cuda")
+    ids = _dev(np.arange(4, dtype=np.uint32))
+    with pytest.raises(sw.SwError):      # capacity not a power of two
+        sw.sw_junctions_clear(ctx, keys, counts, 6)
+    with pytest.raises(sw.SwError):      # min_intron below 4
+        sw.sw_detect_junctions(ctx, db, ids, 4, _dev(aln), _dev(ops), 48, 30, 3, keys, counts, 8)
+
+
+@pytest.fixture(scope="module")
+def spliced_long():
+    long_b, seed_b, truth = synth.spliced_long(n_reads=240, ref_len=1_500_000,
+                                               seed=synth.BASE_SEED + 61)
+    return long_b, seed_b, truth
+
+
+def _oracle_chain(long_b, seed_b, truth, p):
+    """The spliced pass computed by the oracle alone."""
+    ns = seed_b.n_reads
+    res, _ = oracle.align_batch(seed_b, SEED_SCORING, mode=0)
+    rid = seed_b.windows["read_id"].astype(np.int64)
+    best = np.full(ns, -1, np.int64)
+    np.maximum.at(best, rid, res["score"].astype(np.int64))
+    bp = np.full(ns, 0xFFFFFFFF, np.int64)
+    idx = np.nonzero(res["score"] == best[rid])[0][::-1]
+    bp[rid[idx]] = idx
+    bp = bp.astype(np.uint32)
+    assert (bp != 0xFFFFFFFF).all()          # every seed has windows
+    sa, _ = oracle.align_batch(seed_b, SEED_SCORING, mode=1, sel=bp)
+    cals = jr.seed_cals(seed_b.windows, bp, sa, truth["seed_read"], p["min_seed_score"])
+    joined = jr.join_cals(cals, long_b.n_reads, len(long_b.ref), ext=p["ext"],
+                          max_gap=p["max_gap"])
+    win = np.array([(r, b, n, s, 0) for r, b, n, s in joined], dtype=synth.WINDOW_DTYPE)
+    lb = synth.Batch(ref=long_b.ref, reads=long_b.reads, read_off=long_b.read_off,
+                     read_len=long_b.read_len, windows=win, truth={})
+    lres, _ = oracle.align_batch(lb, LONG_SCORING, mode=0)
+    nl = long_b.n_reads
+    lrid = win["read_id"].astype(np.int64)
+    lbest = np.full(nl, -1, np.int64)
+    np.maximum.at(lbest, lrid, lres["score"].astype(np.int64))
+    lbp = np.full(nl, 0xFFFFFFFF, np.int64)
+    lidx = np.nonzero(lres["score"] == lbest[lrid])[0][::-1]
+    lbp[lrid[lidx]] = lidx
+    lbp = lbp.astype(np.uint32)
+    has = lbp != 0xFFFFFFFF
+    la = np.zeros(nl, oracle.RESULT_DTYPE)
+    la["score"] = -1
+    lops = np.zeros((nl, p["ops_stride"]), np.uint32)
+    if has.any():
+        a, o = oracle.align_batch(lb, LONG_SCORING, mode=1, sel=lbp[has],
+                                  ops_stride=p["ops_stride"])
+        la[has] = a
+        lops[has] = o
+    ref_codes = jr.codes_of(long_b.ref.tobytes())
+    lists, det_ops = [], lops.copy()
+    for r in np.nonzero(has)[0]:
+        a = la[r]
+        if a["score"] < p["min_score"] or a["status"]:
+            continue
+        w = win[lbp[r]]
+        t = ref_codes[int(w["ref_begin"]):int(w["ref_begin"]) + int(w["len"])]
+        n = int(a["n_ops"])
+        new, js = jr.detect(t, lops[r, :n], int(a["ref_begin"]), p["min_intron"],
+                            int(w["ref_begin"]))
+        det_ops[r, :n] = new
+        lists.append(js)
+    return dict(bp=bp, cals=cals, joined=joined, lbp=lbp, lbest=lbest, la=la, lops=det_ops,
+                table=dict(jr.count(lists)))
+
+
+def test_spliced_pass_vs_oracle(ctx, spliced_long):
+    long_b, seed_b, truth = spliced_long
+    p = dict(min_seed_score=100, ext=30, max_gap=5000, min_score=100, min_intron=MIN_INTRON,
+             ops_stride=256)
+    want = _oracle_chain(long_b, seed_b, truth, p)
+    seed_db = sw.DeviceBatch.from_synth(ctx, seed_b)
+    long_db = sw.DeviceBatch(ctx, None, long_b.reads, long_b.read_off, long_b.read_len,
+                             np.zeros(0, sw.WINDOW_DTYPE), ref2b=(seed_db.ref2b, seed_db.ref_len))
+    sp = SplicedPass(ctx, seed_db, truth["seed_read"], long_db, min_seed_score=100, ext=30,
+                     max_gap=5000, min_score=100, min_intron=MIN_INTRON, table_capacity=1 << 16,
+                     ops_stride=256, tb_scratch_mb=4096)
+    sp.run()
+    torch.cuda.synchronize()
+    # seeds and their CALs
+    assert (sp.seeds.best_pair.cpu().numpy().view(np.uint32) == want["bp"]).all()
+    got_cals = sp.cals.cpu().numpy().view(CAL_DTYPE)
+    assert _cal_tuples(got_cals) == want["cals"]
+    # joined windows
+    w = sp.windows()
+    assert [(int(x["read_id"]), int(x["ref_begin"]), int(x["len"]), int(x["strand"]))
+            for x in w] == want["joined"]
+    assert len(w) >= long_b.n_reads and int(w["len"].max()) > 2000
+    # whole-read alignments
+    bp, bs, aln, ops, nj = sp.results()
+    assert (bp == want["lbp"]).all()
+    assert (bs == want["lbest"]).all()
+    has = want["lbp"] != 0xFFFFFFFF
+    for f in ("score", "read_begin", "read_end", "ref_begin", "ref_end", "n_ops", "status"):
+        assert (aln[f][has] == want["la"][f][has]).all(), f
+    for r in np.nonzero(has)[0]:
+        n = int(aln["n_ops"][r])
+        assert (ops[r, :n] == want["lops"][r, :n]).all(), r
+    # junctions
+    got = {(int(j["start"]), int(j["end"]), int(j["strand"])): int(j["count"])
+           for j in sp.junctions()}
+    assert got == want["table"]
+    truth_j = {(int(a), int(b), int(s)) for a, b, s in truth["junctions"]}
+    found = set(got) & truth_j
+    assert len(found) >= 0.8 * len(truth_j), (len(found), len(truth_j))
+    assert len(set(got) - truth_j) <= 0.05 * len(got)
