@@ -199,7 +199,7 @@ def test_traceback_band_paired_mates(ctx):
 
 
 @pytest.mark.parametrize("sc", [(2, -3, -4, -4), (1, 0, -2, -1), (3, -1, -5, -2), (127, -127, -127, 0),
-                                (5, -4, -10, -10)])
+                                (5, -4, -10, -10), (5, -4, -20, 0)])
 def test_scoring_schemes(ctx, sc):
     b = edge_batch(13, [1, 17, 64, 100, 130, 300], [1, 16, 65, 300], div=0.1)
     ref, rops = oracle.align_batch(b, sc, mode=1)
