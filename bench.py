@@ -407,7 +407,9 @@ def bench_autotune_mixed(args):
     ctx = sw.sw_ctx_create(0)                # its own context: the tuning stays here
     try:
         b = _mixed_lengths(20130301 + 71, 200_000)
-        sample = _mixed_lengths(20130301 + 72, 50_000)
+        # the sample has the batch's size: how many pairs a class holds decides
+        # how well a tile fills the GPU
+        sample = _mixed_lengths(20130301 + 72, 200_000)
         db = sw.DeviceBatch.from_synth(ctx, b)
         dbs = sw.DeviceBatch.from_synth(ctx, sample)
         hits = torch.empty((b.n_pairs, 3), dtype=torch.int32, device="cuda")
@@ -430,7 +432,7 @@ def bench_autotune_mixed(args):
         cells = b.cells()
         return {
             "workload": "200,000 reads of 20-600 nt (eleven lengths) x 1-4 windows of 200-800 nt; "
-                        "tuned on a separate 50,000-read sample",
+                        "tuned on a separate 200,000-read sample",
             "pairs": b.n_pairs, "cells": cells,
             "default_ms": round(ms_def, 3), "tuned_ms": round(ms_tuned, 3),
             "speedup": round(ms_def / ms_tuned, 4),
@@ -586,6 +588,195 @@ def bench_spliced(ctx, args):
         "seeds_aligned": int(np.count_nonzero(aln["score"] > 0)),
         "generation_seconds": round(t_gen, 1),
         "filtered": filtered,
+    }
+
+
+def bench_junctions(args):
+    """Splice junctions from spliced long reads (stage E tasks i-iv): seeds
+    aligned against their windows, CALs, joined windows, every long read
+    aligned against its joined windows with gap extension 0, junctions detected
+    and counted on the device; sensitivity and precision against the planted
+    introns."""
+    import torch
+
+    import paper_1304_0681_amd as sw
+    import synth
+    from paper_1304_0681_amd.splice import SplicedPass
+
+    t0 = time.perf_counter()
+    long_b, seed_b, truth = synth.spliced_long(n_reads=args.junction_reads)
+    t_gen = time.perf_counter() - t0
+    ctx = sw.sw_ctx_create(0)       # its own context: a 16 GiB traceback scratch
+    try:
+        seed_db = sw.DeviceBatch.from_synth(ctx, seed_b)
+        long_db = sw.DeviceBatch(ctx, None, long_b.reads, long_b.read_off, long_b.read_len,
+                                 np.zeros(0, sw.WINDOW_DTYPE),
+                                 ref2b=(seed_db.ref2b, seed_db.ref_len))
+        sp = SplicedPass(ctx, seed_db, truth["seed_read"], long_db, table_capacity=1 << 21)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        phase = np.zeros(5)
+        wall = []
+        for rep in range(1 + args.junction_steps):
+            sp.clear()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ev[0].record()
+            sp.run_seeds()
+            ev[1].record()
+            sp.run_cals()
+            ev[2].record()
+            sw.sw_batch_score(ctx, sp.long_view, sp.long_scoring, 0, sp.hits)
+            sw.sw_best_per_read(ctx, sp.long_view, sp.hits, sp.min_score, sp.best_pair,
+                                sp.best_score, None)
+            ev[3].record()
+            sw.sw_batch_traceback(ctx, sp.long_view, sp.long_scoring, sp.best_pair, sp.n_long,
+                                  sp.aln, sp.ops, sp.ops_stride)
+            ev[4].record()
+            sp.run_junctions()
+            ev[5].record()
+            torch.cuda.synchronize()
+            if rep >= 1:
+                wall.append(time.perf_counter() - t1)
+                phase += [ev[i].elapsed_time(ev[i + 1]) for i in range(5)]
+        phase /= args.junction_steps
+        t_step = float(np.mean(wall))
+        w = sp.windows()
+        bp, bs, aln, ops, nj = sp.results()
+        j = sp.junctions()
+        dropped = int(sp.dropped.item())
+        m = long_b.read_len[w["read_id"]].astype(np.int64)
+        n = np.minimum(w["len"].astype(np.int64),
+                       len(long_b.ref) - w["ref_begin"].astype(np.int64))
+        long_cells = int((m * n).sum())
+        ok = bp < len(w)
+        tb_cells = int((m[bp[ok]] * n[bp[ok]]).sum())
+        truth_j = {(int(a), int(b), int(s)) for a, b, s in truth["junctions"]}
+        got = {(int(r["start"]), int(r["end"]), int(r["strand"])) for r in j}
+        tp = len(got & truth_j)
+        # alignments that report a junction: the run's bytes (ops read and
+        # written, record, window, pair id) are the detection's whole traffic
+        det_bytes = int(4 * 2 * aln["n_ops"][ok].astype(np.int64).sum()) + 44 * int(ok.sum())
+        return {
+            "workload": f"splice junctions: {args.junction_reads} spliced reads of 400-800 nt "
+                        f"(2-4 exons of 50-300 nt, introns 50-5000 nt with GT-AG or CT-AC, both "
+                        f"gene strands, 16 Mb reference), 100-nt seeds with 4-12 windows of "
+                        f"200-1000 nt each; seeds +5/-4/-10/-1, whole reads +5/-4/-20/0",
+            "reads": long_b.n_reads, "seeds": seed_b.n_reads, "seed_pairs": seed_b.n_pairs,
+            "joined_windows": int(len(w)), "joined_window_len_mean": round(float(w["len"].mean()), 1),
+            "joined_window_len_max": int(w["len"].max()),
+            "ms_per_step": round(t_step * 1e3, 3),
+            "reads_per_s": round(long_b.n_reads / t_step, 1),
+            "phase_ms": {"seeds_score_best_traceback": round(phase[0], 3),
+                         "cals_and_join": round(phase[1], 3),
+                         "long_score_and_best": round(phase[2], 3),
+                         "long_traceback": round(phase[3], 3),
+                         "junction_detect": round(phase[4], 4)},
+            "long_score_cells": long_cells,
+            "long_score_gcups": round(long_cells / (phase[2] / 1e3) / 1e9, 1),
+            "long_traceback_cells": tb_cells,
+            "long_traceback_gcups": round(tb_cells / (phase[3] / 1e3) / 1e9, 1),
+            "junction_detect_gb_per_s": round(det_bytes / (phase[4] / 1e3) / 1e9, 1),
+            "reads_aligned": int((bs >= sp.min_score).sum()),
+            "truth_junctions": len(truth_j), "junctions_found": len(got), "true_positives": tp,
+            "sensitivity": round(tp / max(len(truth_j), 1), 4),
+            "precision": round(tp / max(len(got), 1), 4),
+            "junction_reports": int(j["count"].sum()) if len(j) else 0,
+            "table_dropped": dropped,
+            "generation_seconds": round(t_gen, 1),
+        }
+    finally:
+        sw.sw_ctx_destroy(ctx)
+
+
+def bench_seeker(ctx, args):
+    """Candidate windows found on the device (stages C, D and E tasks i-ii) for
+    the reads of the headline workload, in place of the generator's windows:
+    k-mer index, seeds, regions, CALs, joined windows, then SW and the best
+    window of every read."""
+    import torch
+
+    import paper_1304_0681_amd as sw
+    import synth
+    from paper_1304_0681_amd.seeker import CandidateSeeker, KmerIndex
+
+    b = synth.config2(n_reads=args.seeker_reads)
+    db = sw.DeviceBatch(ctx, b.ref, b.reads, b.read_off, b.read_len,
+                        np.zeros(0, sw.WINDOW_DTYPE))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t_idx = []
+    for _ in range(3):
+        ev[0].record()
+        idx = KmerIndex(ctx, db.ref2b, db.ref_len, k=15)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t_idx.append(ev[0].elapsed_time(ev[1]))
+    cs = CandidateSeeker(ctx, db, idx)
+    hits = torch.empty((cs.n_cals, 3), dtype=torch.int32, device="cuda")
+    bp = torch.empty(b.n_reads, dtype=torch.int32, device="cuda")
+    bs = torch.empty(b.n_reads, dtype=torch.int32, device="cuda")
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    phase = np.zeros(5)
+    wall = []
+    for rep in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs[0].record()
+        cs.run_regions()
+        evs[1].record()
+        cs.run_cals()
+        evs[2].record()
+        cs.run_join()
+        evs[3].record()
+        sw.sw_batch_score(ctx, cs.view, SCORING, 0, hits)
+        evs[4].record()
+        sw.sw_best_per_read(ctx, cs.view, hits, 0, bp, bs)
+        evs[5].record()
+        torch.cuda.synchronize()
+        if rep >= args.warmup:
+            wall.append(time.perf_counter() - t0)
+            phase += [evs[i].elapsed_time(evs[i + 1]) for i in range(5)]
+    phase /= args.steps
+    t_step = float(np.mean(wall))
+    w = cs.windows()
+    end = cs.read_end.cpu().numpy().view(np.uint64)
+    n_regions = int(end[-1])
+    bpn = bp.cpu().numpy().view(np.uint32)
+    bsn = bs.cpu().numpy()
+    tr = b.truth
+    real = ~tr["is_random"]
+    ok = bpn < len(w)
+    wb = np.zeros(b.n_reads, np.int64)
+    wl = np.zeros(b.n_reads, np.int64)
+    ws = np.zeros(b.n_reads, np.int64)
+    wb[ok] = w["ref_begin"][bpn[ok]]
+    wl[ok] = w["len"][bpn[ok]]
+    ws[ok] = w["strand"][bpn[ok]]
+    o0 = tr["origin"].astype(np.int64)
+    o1 = o0 + tr["span"].astype(np.int64)
+    found = ok & (ws == tr["strand"]) & (np.minimum(o1, wb + wl) - np.maximum(o0, wb) >= 50)
+    m = b.read_len[w["read_id"]].astype(np.int64)
+    n = np.minimum(w["len"].astype(np.int64), len(b.ref) - w["ref_begin"].astype(np.int64))
+    cells = int((m * n).sum())
+    idx_bytes = idx.nbytes
+    return {
+        "workload": f"candidate windows found on the device for {b.n_reads} x 100-nt reads "
+                    f"(4 Mb GC-40% reference, 1% substitutions, 0.1% indels, 5% random reads): "
+                    f"15-nt seeds in two phases (step 12, offset 7), exact 15-mer index, regions "
+                    f"merged within 50 nt into CALs longer than 20 nt, CALs extended by 30 and "
+                    f"joined within 5,000 nt, SW of every read against its windows, best window",
+        "reads": b.n_reads,
+        "index": {"k": 15, "bytes": idx_bytes, "build_ms": round(float(np.median(t_idx)), 3)},
+        "ms_per_step": round(t_step * 1e3, 3),
+        "reads_per_s": round(b.n_reads / t_step, 1),
+        "phase_ms": {"regions": round(phase[0], 3), "cal_seeker": round(phase[1], 3),
+                     "join": round(phase[2], 3), "sw_score": round(phase[3], 3),
+                     "best": round(phase[4], 3)},
+        "regions": n_regions, "windows": int(len(w)),
+        "windows_per_read": round(len(w) / b.n_reads, 3),
+        "cells": cells, "gcups_score": round(cells / (phase[3] / 1e3) / 1e9, 1),
+        "origin_is_best_window": round(float(found[real].mean()), 5),
+        "mapped_fraction": round(float((bsn >= 250).mean()), 5),
+        "random_reads_mapped": int(((bsn >= 250) & ~real).sum()),
     }
 
 
@@ -803,6 +994,11 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--no-spliced", action="store_true", help="skip the spliced-seed traceback pass")
     ap.add_argument("--spliced-reads", type=int, default=200_000)
+    ap.add_argument("--no-seeker", action="store_true", help="skip the device candidate seeker")
+    ap.add_argument("--seeker-reads", type=int, default=1_000_000)
+    ap.add_argument("--no-junctions", action="store_true", help="skip the splice-junction pass")
+    ap.add_argument("--junction-reads", type=int, default=50_000)
+    ap.add_argument("--junction-steps", type=int, default=3)
     ap.add_argument("--no-stream", action="store_true", help="skip the paired-read stream")
     ap.add_argument("--stream-frags", type=int, default=500_000,
                     help="fragments per chunk (2 mates each)")
@@ -963,6 +1159,12 @@ def main():
     if not args.no_spliced:
         log("spliced seeds ...")
         out["spliced"] = bench_spliced(ctx, args)
+    if not args.no_seeker:
+        log("candidate seeker ...")
+        out["seeker"] = bench_seeker(ctx, args)
+    if not args.no_junctions:
+        log("splice junctions ...")
+        out["junctions"] = bench_junctions(args)
     if not args.no_stream:
         log("paired-read stream ...")
         out["stream"] = bench_stream(ctx, args, gen)

@@ -271,6 +271,79 @@ sw_status sw_join_cals(sw_ctx *ctx, const sw_cal *d_cals, uint32_t n_cals, uint3
                        uint64_t ref_len, uint32_t ext, uint32_t max_gap, sw_window *d_win_out,
                        uint32_t *d_n_out, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Region seeker and CAL seeker (Sec. 2, "Stage C: Region Seeker" and
+ * "Stage D: CAL Seeker").
+ *
+ * Every read is cut into seeds of k bases in two phases (starts 0, step,
+ * 2 step, ... and offset, offset + step, ...; k = 15, step = 12, offset = 7 give
+ * a 100-nt read the paper's 8 + 7 seeds); each seed is mapped exactly onto
+ * the reference through a k-mer index, on both strands, and every match is a
+ * region; a read's regions closer than merge_gap bases are merged, and a
+ * merged region longer than min_len bases is a CAL.  The CALs feed
+ * sw_join_cals (stage E tasks i, ii), whose windows feed sw_batch_score.
+ * ------------------------------------------------------------------------- */
+
+/* Exact k-mer index of a packed reference, for k in [4, 15], in one
+ * caller-owned device buffer of sw_kmer_index_bytes bytes: a 32-bit start
+ * offset for every one of the 4^k codes plus one (code c's positions are
+ * pos[start[c] .. start[c + 1])), then the positions (one 32-bit word per
+ * k-mer of the reference, L - k + 1 of them, in no particular order within a
+ * code).  A k-mer's code holds base i at bits 2i.  For k = 15 the offsets take
+ * 4 GiB.  SW_E_RANGE if k is out of range or the reference holds 2^32 or more
+ * k-mers. */
+sw_status sw_kmer_index_bytes(uint64_t ref_len, uint32_t k, uint64_t *bytes);
+/* Build the index (counting sort on the device; context scratch of about
+ * 4^k / 1024 bytes).  index_bytes must be at least sw_kmer_index_bytes. */
+sw_status sw_kmer_index_build(sw_ctx *ctx, const uint32_t *d_ref2b, uint64_t ref_len, uint32_t k,
+                              void *d_index, uint64_t index_bytes, void *stream);
+
+typedef struct {
+    uint32_t k;         /* seed length, the index's k */
+    uint32_t step;      /* distance between the seeds of one phase, >= 1 */
+    uint32_t offset;    /* first base of the second phase */
+    uint32_t max_occ;   /* a seed matching more places than this on a strand gives
+                           no region there */
+} sw_seed_params;
+
+/* One region: reference bases [first, first + k) match a seed exactly; strand 1:
+ * the seed's reverse complement matches there, and read_pos is the seed's
+ * position in the read's reverse complement (so first - read_pos is the read's
+ * diagonal on either strand).  8 bytes; the read is the segment it lies in. */
+typedef struct {
+    uint32_t first;
+    uint16_t read_pos;
+    uint8_t strand;
+    uint8_t reserved;   /* written as 0 */
+} sw_region;
+
+/* Regions of every read of `reads` (its reads only: the windows and reference
+ * are not used) against the index d_index (built with sp->k).  Read r's
+ * regions are d_regions[read_end[r - 1] .. read_end[r]) (read_end[-1] = 0;
+ * d_read_end: device uint64 array of n_reads), in seed order (first phase
+ * first), strand 0 before strand 1 for each seed, reference positions
+ * ascending.  Regions at or beyond cap are counted in read_end but not written.
+ * Reads outside the packed reads get none.  Context scratch: about 4 bytes per
+ * read. */
+sw_status sw_seed_regions(sw_ctx *ctx, const sw_batch *reads, const void *d_index,
+                          const sw_seed_params *sp, sw_region *d_regions, uint64_t cap,
+                          uint64_t *d_read_end, void *stream);
+
+/* CALs of every read from its regions (the first SW_SEEKER_MAX_REGIONS of
+ * them that lie below cap): per strand, regions sorted by first base merge
+ * while fewer than merge_gap bases lie strictly between the next region and
+ * the merged region's end (overlap merges); a merged region [first, last] is
+ * a CAL when last - first + 1 > min_len.  Read r's CALs go to
+ * d_cals[r * SW_SEEKER_MAX_CALS ...], ordered by (strand, first), at most
+ * SW_SEEKER_MAX_CALS of them (the first in that order), and the remaining
+ * slots get invalid CALs {r, 0, 0, 0, 0}: the array is grouped by read, as
+ * sw_join_cals takes it.  k is the regions' length. */
+#define SW_SEEKER_MAX_CALS 16
+#define SW_SEEKER_MAX_REGIONS 2048
+sw_status sw_cal_seeker(sw_ctx *ctx, const sw_region *d_regions, const uint64_t *d_read_end,
+                        uint32_t n_reads, uint64_t cap, uint32_t k, uint32_t merge_gap,
+                        uint32_t min_len, sw_cal *d_cals, void *stream);
+
 /* Junction table: caller-owned device arrays d_keys[capacity] (uint64) and
  * d_counts[capacity] (uint32), capacity a power of two in [1, 2^31].  Zero
  * them with sw_junctions_clear before first use; sw_detect_junctions adds to
@@ -462,8 +535,12 @@ sw_status sw_filter_candidates(sw_ctx *ctx, const sw_batch *batch, const sw_mlp 
  *      default tile that holds it; a bound moves when the two classes it
  *      separates get faster;
  *   2. tiles: for every populated class, the three smallest tiles that hold
- *      its bound, at 1, 2 or 4 workgroups per compute unit.
- * The tiles searched are the classes' default tiles.  Results are identical
+ *      its bound, at 1, 2 or 4 workgroups per compute unit;
+ *   3. the whole choice and the defaults are timed again side by side
+ *      (2 x repeats calls each); unless the choice is at least 1 % faster over
+ *      all classes, the defaults are kept.
+ * Tune on a sample of the size the calls will have: how many pairs a class
+ * holds decides how well a tile fills the GPU.  The tiles searched are the classes' default tiles.  Results are identical
  * for every candidate: only time changes.  Packed int16 runs on the 4 x 25
  * tile of the 65-100-base class with its default bounds.  out[SW_NUM_CLASSES]
  * (host, may be NULL) receives the choice (m_max: the tuned class bound).
@@ -477,10 +554,11 @@ typedef struct {
     int32_t blocks_per_cu;  /* chosen workgroups (4 waves) per compute unit */
     int32_t path;           /* 0 class not run, 1 int32, 2 int32 with ends, 3 packed int16 */
     int32_t candidates;     /* candidates timed */
-    float ms;               /* time of the class per call under the choice (0: empty) */
-    float ms_default;       /* time of the class under the default bounds and tiles
-                               (0: empty there); when a bound moved the classes hold
-                               other pairs, so compare the sums over all classes */
+    float ms;               /* time of the class per call under the choice, from the
+                               final side-by-side timing (0: empty) */
+    float ms_default;       /* time of the class under the default bounds and tiles in
+                               that timing (0: empty there); when a bound moved the
+                               classes hold other pairs, so compare the sums */
 } sw_tune_entry;
 sw_status sw_autotune(sw_ctx *ctx, const sw_batch *sample, const sw_scoring *sc, uint32_t flags,
                       int repeats, sw_tune_entry *out, void *stream);

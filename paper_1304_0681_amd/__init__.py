@@ -35,6 +35,10 @@ CAL_DTYPE = np.dtype([("read_id", "<u4"), ("first", "<u4"), ("last", "<u4"), ("s
                       ("valid", "u1"), ("reserved", "<u2")])
 JUNCTION_DTYPE = np.dtype([("start", "<u8"), ("end", "<u8"), ("count", "<u4"),
                            ("strand", "<u4")])
+REGION_DTYPE = np.dtype([("first", "<u4"), ("read_pos", "<u2"), ("strand", "u1"),
+                         ("reserved", "u1")])
+SW_SEEKER_MAX_CALS = 16
+SW_SEEKER_MAX_REGIONS = 2048
 
 
 class SwError(RuntimeError):
@@ -59,6 +63,11 @@ class sw_batch(ctypes.Structure):
                 ("d_read_off", ctypes.c_void_p), ("d_read_len", ctypes.c_void_p),
                 ("n_reads", ctypes.c_uint32), ("d_win", ctypes.c_void_p),
                 ("n_pairs", ctypes.c_uint32), ("d_n_pairs", ctypes.c_void_p)]
+
+
+class sw_seed_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("step", ctypes.c_uint32), ("offset", ctypes.c_uint32),
+                ("max_occ", ctypes.c_uint32)]
 
 
 class sw_filter_params(ctypes.Structure):
@@ -123,6 +132,11 @@ def lib() -> ctypes.CDLL:
         L.sw_detect_junctions.argtypes = [P, ctypes.POINTER(sw_batch), P, U32, P, P, U32, I32,
                                           U32, P, P, U32, P, P, P]
         L.sw_list_junctions.argtypes = [P, P, P, U32, P, U32, P, P]
+        L.sw_kmer_index_bytes.argtypes = [U64, U32, ctypes.POINTER(ctypes.c_uint64)]
+        L.sw_kmer_index_build.argtypes = [P, P, U64, U32, P, U64, P]
+        L.sw_seed_regions.argtypes = [P, ctypes.POINTER(sw_batch), P,
+                                      ctypes.POINTER(sw_seed_params), P, U64, P, P]
+        L.sw_cal_seeker.argtypes = [P, P, P, U32, U64, U32, U32, U32, P, P]
         L.sw_graph_begin.argtypes = [P, P]
         L.sw_graph_end.argtypes = [P, P, ctypes.POINTER(P)]
         L.sw_graph_launch.argtypes = [P, P, P]
@@ -137,7 +151,8 @@ def lib() -> ctypes.CDLL:
                   "sw_mlp_save", "sw_mlp_load",
                   "sw_mlp_forward", "sw_mlp_grad", "sw_mlp_train_step", "sw_mlp_labels",
                   "sw_filter_candidates", "sw_seed_cals", "sw_join_cals", "sw_junctions_clear",
-                  "sw_detect_junctions", "sw_list_junctions"):
+                  "sw_detect_junctions", "sw_list_junctions", "sw_kmer_index_bytes",
+                  "sw_kmer_index_build", "sw_seed_regions", "sw_cal_seeker"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -358,6 +373,34 @@ def sw_detect_junctions(ctx, batch, d_pair_ids, n, d_aln, d_ops, ops_stride, min
 def sw_list_junctions(ctx, d_keys, d_counts, capacity, d_out, out_cap, d_n, stream=None):
     _check(ctx, lib().sw_list_junctions(ctx, _ptr(d_keys), _ptr(d_counts), int(capacity),
                                         _ptr(d_out), int(out_cap), _ptr(d_n), _stream_ptr(stream)))
+
+
+def sw_kmer_index_bytes(ref_len, k) -> int:
+    n = ctypes.c_uint64(0)
+    st = lib().sw_kmer_index_bytes(int(ref_len), int(k), ctypes.byref(n))
+    if st != SW_OK:
+        raise SwError(st, lib().sw_last_error(None).decode())
+    return int(n.value)
+
+
+def sw_kmer_index_build(ctx, d_ref2b, ref_len, k, d_index, index_bytes, stream=None):
+    _check(ctx, lib().sw_kmer_index_build(ctx, _ptr(d_ref2b), int(ref_len), int(k), _ptr(d_index),
+                                          int(index_bytes), _stream_ptr(stream)))
+
+
+def sw_seed_regions(ctx, batch, d_index, params, d_regions, cap, d_read_end, stream=None):
+    """`params`: (k, step, offset, max_occ) or sw_seed_params."""
+    sp = params if isinstance(params, sw_seed_params) else sw_seed_params(*[int(x) for x in params])
+    _check(ctx, lib().sw_seed_regions(ctx, ctypes.byref(batch.c), _ptr(d_index), ctypes.byref(sp),
+                                      _ptr(d_regions), int(cap), _ptr(d_read_end),
+                                      _stream_ptr(stream)))
+
+
+def sw_cal_seeker(ctx, d_regions, d_read_end, n_reads, cap, k, merge_gap, min_len, d_cals,
+                  stream=None):
+    _check(ctx, lib().sw_cal_seeker(ctx, _ptr(d_regions), _ptr(d_read_end), int(n_reads), int(cap),
+                                    int(k), int(merge_gap), int(min_len), _ptr(d_cals),
+                                    _stream_ptr(stream)))
 
 
 def sw_graph_begin(ctx, stream):

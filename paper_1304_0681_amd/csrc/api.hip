@@ -60,6 +60,9 @@ struct sw_ctx {
     // CAL joining scratch: windows, flags, compaction ids and scan words
     void *join = nullptr;
     size_t join_bytes = 0;
+    // seeker scratch: scan tile sums, per-read region counts
+    void *seek = nullptr;
+    size_t seek_bytes = 0;
     ClassShape shapes[kNumClasses];
     int blocks_per_cu[kNumClasses];
     ClassEdges edges;    // query-length class bounds of the score path
@@ -286,6 +289,7 @@ sw_status sw_ctx_destroy(sw_ctx *ctx)
     if (ctx->tb) keep(hipFree(ctx->tb));
     if (ctx->seg) keep(hipFree(ctx->seg));
     if (ctx->join) keep(hipFree(ctx->join));
+    if (ctx->seek) keep(hipFree(ctx->seek));
     for (auto &ev : ctx->ev)
         if (ev) keep(hipEventDestroy(ev));
     delete ctx;
@@ -928,6 +932,32 @@ sw_status sw_autotune(sw_ctx *ctx, const sw_batch *b, const sw_scoring *sc, uint
                     cur.bpc[c] = t.bpc[c];
                 }
             }
+        }
+        // 3. the choice as a whole against the defaults, both timed again side by
+        //    side: per-class minima over noisy timings favour the candidates, and
+        //    a choice that is not faster in total gives way to the defaults
+        float fin_ms[kNumClasses], d2_ms[kNumClasses];
+        int fin_path[kNumClasses], d2_path[kNumClasses];
+        const int reps2 = std::min(2 * repeats, 100);
+        if ((st = time_choice(ctx, cur, b, sc, flags, (sw_hit *)hits, reps2, stream, fin_ms,
+                              fin_path)) ||
+            (st = time_choice(ctx, def, b, sc, flags, (sw_hit *)hits, reps2, stream, d2_ms,
+                              d2_path)))
+            return bail(st);
+        float fin_sum = 0.f, d2_sum = 0.f;
+        for (int c = 0; c < kNumClasses; ++c) {
+            fin_sum += fin_ms[c];
+            d2_sum += d2_ms[c];
+        }
+        memcpy(def_ms, d2_ms, sizeof def_ms);
+        if (fin_sum < 0.99f * d2_sum) {
+            memcpy(cur_ms, fin_ms, sizeof cur_ms);
+            memcpy(cur_path, fin_path, sizeof cur_path);
+        } else {
+            cur = def;
+            memcpy(cur_ms, d2_ms, sizeof cur_ms);
+            memcpy(cur_path, d2_path, sizeof cur_path);
+            memcpy(populated, populated_def, sizeof populated);
         }
     }
     apply_choice(ctx, cur);
@@ -1616,6 +1646,127 @@ sw_status sw_list_junctions(sw_ctx *ctx, const uint64_t *d_keys, const uint32_t 
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, launch_list(d_keys, d_counts, capacity, d_out, out_cap, d_n,
                              static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Region and CAL seekers.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Offsets part of an index: 4^k + 1 words, rounded up to 256 bytes.
+uint64_t index_offsets_bytes(uint32_t k) { return (4ull * (kmer_index_codes(k) + 1) + 255) & ~255ull; }
+
+sw_status check_seed_params(sw_ctx *ctx, const sw_seed_params *sp)
+{
+    if (!sp)
+        return fail(ctx, SW_E_INVALID, "seed parameters are NULL");
+    if (sp->k < 4 || sp->k > 15)
+        return fail(ctx, SW_E_RANGE, "k must be in [4, 15], got %u", sp->k);
+    if (sp->step == 0)
+        return fail(ctx, SW_E_INVALID, "step must be at least 1");
+    if (sp->offset > 65535)
+        return fail(ctx, SW_E_RANGE, "offset above the longest read");
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sw_status sw_kmer_index_bytes(uint64_t ref_len, uint32_t k, uint64_t *bytes)
+{
+    if (!bytes)
+        return fail(nullptr, SW_E_INVALID, "bytes is NULL");
+    *bytes = 0;
+    if (k < 4 || k > 15)
+        return fail(nullptr, SW_E_RANGE, "k must be in [4, 15], got %u", k);
+    const uint64_t n_pos = ref_len >= k ? ref_len - k + 1 : 0;
+    if (n_pos >= (1ull << 32))
+        return fail(nullptr, SW_E_RANGE, "the reference holds 2^32 or more k-mers");
+    *bytes = index_offsets_bytes(k) + 4 * n_pos;
+    return SW_OK;
+}
+
+sw_status sw_kmer_index_build(sw_ctx *ctx, const uint32_t *d_ref2b, uint64_t ref_len, uint32_t k,
+                              void *d_index, uint64_t index_bytes, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    uint64_t need = 0;
+    sw_status st = sw_kmer_index_bytes(ref_len, k, &need);
+    if (st)
+        return fail(ctx, st, "%s", g_noctx_err.c_str());
+    if (!d_index || (ref_len && !d_ref2b))
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    if (index_bytes < need)
+        return fail(ctx, SW_E_RANGE, "index buffer of %llu bytes, %llu needed",
+                    (unsigned long long)index_bytes, (unsigned long long)need);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    void *buf = ctx->seek;
+    size_t have = ctx->seek_bytes;
+    if ((st = ensure(ctx, &buf, &have, 8 * seeker_scan_words(kmer_index_codes(k)))))
+        return st;
+    ctx->seek = buf;
+    ctx->seek_bytes = have;
+    uint32_t *starts = static_cast<uint32_t *>(d_index);
+    uint32_t *pos = reinterpret_cast<uint32_t *>(static_cast<char *>(d_index) + index_offsets_bytes(k));
+    HIP_TRY(ctx, launch_index_build(d_ref2b, ref_len, k, starts, pos, static_cast<uint32_t *>(buf),
+                                    static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_seed_regions(sw_ctx *ctx, const sw_batch *reads, const void *d_index,
+                          const sw_seed_params *sp, sw_region *d_regions, uint64_t cap,
+                          uint64_t *d_read_end, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    if (!reads)
+        return fail(ctx, SW_E_INVALID, "batch is NULL");
+    sw_status st = check_seed_params(ctx, sp);
+    if (st)
+        return st;
+    if (reads->n_reads == 0)
+        return SW_OK;
+    if (!reads->d_read_len || !reads->d_read_off || !reads->d_reads2b || !d_index || !d_read_end ||
+        (cap && !d_regions))
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const size_t cnt_bytes = align_up(4ull * reads->n_reads);
+    void *buf = ctx->seek;
+    size_t have = ctx->seek_bytes;
+    if ((st = ensure(ctx, &buf, &have, cnt_bytes + 8 * seeker_scan_words(reads->n_reads))))
+        return st;
+    ctx->seek = buf;
+    ctx->seek_bytes = have;
+    const uint32_t *starts = static_cast<const uint32_t *>(d_index);
+    const uint32_t *pos = reinterpret_cast<const uint32_t *>(static_cast<const char *>(d_index) +
+                                                             index_offsets_bytes(sp->k));
+    uint32_t *cnt = static_cast<uint32_t *>(buf);
+    uint64_t *tsum = reinterpret_cast<uint64_t *>(static_cast<char *>(buf) + cnt_bytes);
+    HIP_TRY(ctx, launch_regions(*reads, starts, pos, *sp, d_regions, cap, cnt, d_read_end, tsum,
+                                static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_cal_seeker(sw_ctx *ctx, const sw_region *d_regions, const uint64_t *d_read_end,
+                        uint32_t n_reads, uint64_t cap, uint32_t k, uint32_t merge_gap,
+                        uint32_t min_len, sw_cal *d_cals, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    if (n_reads == 0)
+        return SW_OK;
+    if (!d_read_end || !d_cals || (cap && !d_regions))
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    if (k < 1 || k > 65535)
+        return fail(ctx, SW_E_RANGE, "region length out of range");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_cal_seek(d_regions, d_read_end, n_reads, cap, k, merge_gap, min_len, d_cals,
+                                 static_cast<hipStream_t>(stream)));
     return SW_OK;
 }
 

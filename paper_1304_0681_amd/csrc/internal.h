@@ -143,4 +143,16 @@ hipError_t launch_table_clear(uint64_t *keys, uint32_t *counts, uint32_t cap, hi
 hipError_t launch_list(const uint64_t *keys, const uint32_t *counts, uint32_t cap, sw_junction *out,
                        uint32_t out_cap, uint32_t *d_n, hipStream_t st);
 
+// Region and CAL seekers (seeker.hip).
+uint64_t kmer_index_codes(uint32_t k);
+uint64_t seeker_scan_words(uint64_t n);
+hipError_t launch_index_build(const uint32_t *ref, uint64_t ref_len, uint32_t k, uint32_t *starts,
+                              uint32_t *pos, uint32_t *tsum, hipStream_t st);
+hipError_t launch_regions(const sw_batch &b, const uint32_t *starts, const uint32_t *pos,
+                          const sw_seed_params &sp, sw_region *out, uint64_t cap,
+                          uint32_t *cnt, uint64_t *read_end, uint64_t *tsum, hipStream_t st);
+hipError_t launch_cal_seek(const sw_region *reg, const uint64_t *read_end, uint32_t n_reads,
+                           uint64_t cap, uint32_t k, uint32_t merge_gap, uint32_t min_len,
+                           sw_cal *cals, hipStream_t st);
+
 }  // namespace hpgsw

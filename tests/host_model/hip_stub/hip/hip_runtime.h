@@ -1,9 +1,10 @@
 // Host stand-in for the few HIP runtime declarations the score and splice
 // kernels' sources use, so that the unmodified kernel files compile as plain
-// C++ for the CPU models (tests/host_model/score_model.cpp and
-// splice_model.cpp).  Kernel launches compile to nothing; the models call the
-// kernel functions themselves, one thread (or one loop step) per lane.  Cross-lane operations and the AMDGPU builtins the kernels use are
-// declared here and defined by the model.
+// C++ for the CPU models (tests/host_model/score_model.cpp, splice_model.cpp
+// and seeker_model.cpp).  Kernel launches compile to nothing; the models call
+// the kernel functions themselves, one thread (or one loop step) per lane.
+// Cross-lane operations, barriers and the AMDGPU builtins the kernels use are
+// declared here and defined by the models.
 #pragma once
 
 #include <stdint.h>
@@ -13,6 +14,9 @@
 #define __host__
 #define __forceinline__ inline __attribute__((always_inline))
 #define __launch_bounds__(...)
+// one block runs at a time in the models, so a block's shared arrays can be
+// function statics
+#define __shared__ static
 
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
@@ -33,7 +37,7 @@ inline int2 make_int2(int x, int y) { return int2{x, y}; }
 struct ModelIdx {
     unsigned x, y, z;
 };
-extern thread_local ModelIdx threadIdx, blockIdx, gridDim;
+extern thread_local ModelIdx threadIdx, blockIdx, gridDim, blockDim;
 
 inline int max(int a, int b) { return a > b ? a : b; }
 inline int min(int a, int b) { return a < b ? a : b; }
@@ -47,11 +51,16 @@ int __shfl(int v, int src, int width = 64);
 int __shfl_xor(int v, int mask, int width = 64);
 uint64_t __shfl_xor(uint64_t v, int mask, int width = 64);
 uint32_t atomicAdd(uint32_t *p, uint32_t v);
+uint32_t atomicSub(uint32_t *p, uint32_t v);
 unsigned long long atomicCAS(unsigned long long *p, unsigned long long cmp, unsigned long long v);
 uint32_t model_perm(uint32_t hi, uint32_t lo, uint32_t sel);
 uint32_t model_alignbit(uint32_t hi, uint32_t lo, uint32_t shift);
 int model_sbfe(int src, int offset, int width);
 inline void __threadfence_block() {}
+void __syncthreads();
+void model_wave_barrier();
+#define __builtin_amdgcn_wave_barrier model_wave_barrier
+#define __builtin_amdgcn_fence(...) __atomic_thread_fence(__ATOMIC_SEQ_CST)
 
 #define __builtin_amdgcn_update_dpp model_update_dpp
 #define __builtin_amdgcn_perm model_perm

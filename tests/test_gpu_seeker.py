@@ -1,0 +1,151 @@
+"""Region and CAL seekers on the GPU: the k-mer index (k = 10 in full, k = 15
+by counts, bucket membership and a permutation check), the regions of every
+read in exact order, the CALs, and the joined windows, against the oracle
+(oracle/seeker_ref.py, oracle/junction_ref.py); then the windows found this
+way scored and the best window checked against the reads' origins."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1304_0681_amd as sw
+import synth
+from oracle import junction_ref as jr
+from oracle import seeker_ref as sr
+from paper_1304_0681_amd.seeker import CandidateSeeker, KmerIndex
+from seeker_inputs import reads_from, reference_with_repeats
+
+pytestmark = pytest.mark.gpu
+
+SC = (5, -4, -10, -1)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch.cuda.set_device(0)
+    c = sw.sw_ctx_create(0)
+    yield c
+    sw.sw_ctx_destroy(c)
+
+
+def _db(ctx, ref, reads):
+    b = synth.custom(synth.ASCII[ref].tobytes(), [synth.ASCII[q].tobytes() for q in reads], [])
+    return sw.DeviceBatch(ctx, b.ref, b.reads, b.read_off, b.read_len, b.windows)
+
+
+def test_index_k10_exact(ctx):
+    ref = reference_with_repeats(61, 300_000)
+    db = _db(ctx, ref, [ref[:20]])
+    idx = KmerIndex(ctx, db.ref2b, db.ref_len, k=10)
+    starts, pos = idx.arrays()
+    torch.cuda.synchronize()
+    st = starts.cpu().numpy().view(np.uint32).astype(np.int64)
+    p = pos.cpu().numpy().view(np.uint32)
+    want = sr.build_index_fast(ref, 10)
+    assert st[-1] == len(ref) - 9 and (np.diff(st) >= 0).all()
+    got = {c: sorted(p[st[c]:st[c + 1]].tolist()) for c in np.nonzero(np.diff(st))[0]}
+    assert got == want
+
+
+def test_index_k15_counts_and_membership(ctx):
+    ref = reference_with_repeats(62, 2_000_000, families=20)
+    db = _db(ctx, ref, [ref[:20]])
+    idx = KmerIndex(ctx, db.ref2b, db.ref_len, k=15)
+    starts, pos = idx.arrays()
+    torch.cuda.synchronize()
+    n_pos = len(ref) - 14
+    assert int(starts[-1].item()) == n_pos
+    assert bool((starts[1:] >= starts[:-1]).all().item())
+    codes = sr.position_codes(ref, 15)
+    uniq, cnt = np.unique(codes, return_counts=True)
+    u = torch.from_numpy(uniq).cuda()
+    got_cnt = (starts[u + 1].long() - starts[u].long()).cpu().numpy()
+    assert (got_cnt == cnt).all() and int(cnt.sum()) == n_pos
+    # every slot's position spells its bucket's code, and positions are a permutation
+    pl = pos.long()
+    assert bool((torch.sort(pl).values == torch.arange(n_pos, device="cuda")).all().item())
+    bucket = torch.repeat_interleave(u, torch.from_numpy(cnt).cuda())
+    assert bool((torch.from_numpy(codes).cuda()[pl] == bucket).all().item())
+
+
+@pytest.fixture(scope="module")
+def seeded(ctx):
+    ref = reference_with_repeats(63, 1_000_000, families=10, copies=(2, 8))
+    reads, origins, strands = reads_from(64, ref, 6000)
+    db = _db(ctx, ref, reads)
+    idx = KmerIndex(ctx, db.ref2b, db.ref_len, k=15)
+    cs = CandidateSeeker(ctx, db, idx, max_occ=40, merge_gap=50, min_len=20, ext=30,
+                         max_gap=5000)
+    cs.run()
+    torch.cuda.synchronize()
+    oidx = sr.build_index_fast(ref, 15)
+    return ref, reads, origins, strands, db, cs, oidx
+
+
+def test_regions_exact(seeded):
+    ref, reads, origins, strands, db, cs, oidx = seeded
+    regs, end = cs.region_list()
+    b = 0
+    for r, q in enumerate(reads):
+        want = sr.regions(q, oidx, 15, 12, 7, 40)
+        e = int(end[r])
+        got = [(int(x["strand"]), int(x["first"]), int(x["first"]) + 14, int(x["read_pos"]))
+               for x in regs[b:e]]
+        assert got == want, r
+        b = e
+    assert b > 50_000
+
+
+def _oracle_cals(reads, oidx):
+    out = []
+    for r, q in enumerate(reads):
+        c = sr.cals(r, sr.regions(q, oidx, 15, 12, 7, 40), 50, 20)
+        out += c + [(r, 0, 0, 0, 0)] * (sw.SW_SEEKER_MAX_CALS - len(c))
+    return out
+
+
+def test_cals_and_windows_exact(seeded):
+    ref, reads, origins, strands, db, cs, oidx = seeded
+    got = cs.cals.cpu().numpy().view(jr_dtype())
+    want = _oracle_cals(reads, oidx)
+    assert [(int(c["read_id"]), int(c["first"]), int(c["last"]), int(c["strand"]),
+             int(c["valid"])) for c in got] == want
+    w = cs.windows()
+    jw = jr.join_cals(want, len(reads), len(ref), ext=30, max_gap=5000)
+    assert [(int(x["read_id"]), int(x["ref_begin"]), int(x["len"]), int(x["strand"]))
+            for x in w] == jw
+
+
+def jr_dtype():
+    return np.dtype([("read_id", "<u4"), ("first", "<u4"), ("last", "<u4"), ("strand", "u1"),
+                     ("valid", "u1"), ("reserved", "<u2")])
+
+
+def test_found_windows_hold_the_origins(ctx, seeded):
+    """Score the windows the seeker found: every read copied from the reference
+    (100 nt or longer) has a window on its own strand over at least half of its
+    origin span, and its best window scores at least 2 per base."""
+    ref, reads, origins, strands, db, cs, oidx = seeded
+    hits = torch.empty((cs.n_cals, 3), dtype=torch.int32, device="cuda")
+    bp = torch.empty(len(reads), dtype=torch.int32, device="cuda")
+    bs = torch.empty(len(reads), dtype=torch.int32, device="cuda")
+    sw.sw_batch_score(ctx, cs.view, SC, 0, hits)
+    sw.sw_best_per_read(ctx, cs.view, hits, 0, bp, bs)
+    torch.cuda.synchronize()
+    w = cs.windows()
+    bsn = bs.cpu().numpy()
+    lens = np.array([len(q) for q in reads])
+    by_read = {}
+    for x in w:
+        by_read.setdefault(int(x["read_id"]), []).append(x)
+    covered = mapped = n = 0
+    for r in range(len(reads)):
+        if origins[r] < 0 or lens[r] < 100:
+            continue
+        n += 1
+        o0, o1 = origins[r], origins[r] + lens[r]
+        covered += any(int(x["strand"]) == strands[r] and
+                       min(o1, int(x["ref_begin"]) + int(x["len"])) - max(o0, int(x["ref_begin"]))
+                       >= 0.5 * lens[r] for x in by_read.get(r, []))
+        mapped += bsn[r] >= 2 * lens[r]
+    assert covered >= 0.995 * n and mapped >= 0.97 * n, (covered, mapped, n)
