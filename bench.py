@@ -612,7 +612,10 @@ def bench_junctions(args):
         long_db = sw.DeviceBatch(ctx, None, long_b.reads, long_b.read_off, long_b.read_len,
                                  np.zeros(0, sw.WINDOW_DTYPE),
                                  ref2b=(seed_db.ref2b, seed_db.ref_len))
-        sp = SplicedPass(ctx, seed_db, truth["seed_read"], long_db, table_capacity=1 << 21)
+        # a 64 GiB traceback scratch: the longest joined window sizes every code slot
+        # of its class, and this budget keeps four waves per SIMD in flight
+        sp = SplicedPass(ctx, seed_db, truth["seed_read"], long_db, table_capacity=1 << 21,
+                         tb_scratch_mb=args.junction_tb_mb)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
         phase = np.zeros(5)
         wall = []
@@ -682,6 +685,7 @@ def bench_junctions(args):
             "precision": round(tp / max(len(got), 1), 4),
             "junction_reports": int(j["count"].sum()) if len(j) else 0,
             "table_dropped": dropped,
+            "traceback_scratch_mb": args.junction_tb_mb,
             "generation_seconds": round(t_gen, 1),
         }
     finally:
@@ -999,6 +1003,8 @@ def main():
     ap.add_argument("--no-junctions", action="store_true", help="skip the splice-junction pass")
     ap.add_argument("--junction-reads", type=int, default=50_000)
     ap.add_argument("--junction-steps", type=int, default=3)
+    ap.add_argument("--junction-tb-mb", type=int, default=65536,
+                    help="traceback scratch (MiB) of the whole-read alignments")
     ap.add_argument("--no-stream", action="store_true", help="skip the paired-read stream")
     ap.add_argument("--stream-frags", type=int, default=500_000,
                     help="fragments per chunk (2 mates each)")
