@@ -762,6 +762,47 @@ def bench_seeker(ctx, args):
     n = np.minimum(w["len"].astype(np.int64), len(b.ref) - w["ref_begin"].astype(np.int64))
     cells = int((m * n).sum())
     idx_bytes = idx.nbytes
+    # stage B first: reads mapped with at most one edit skip the seekers and SW
+    csb = CandidateSeeker(ctx, db, idx, stage_b=True)
+    hits_b = torch.empty((csb.n_cals, 3), dtype=torch.int32, device="cuda")
+    evb = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+    phase_b = np.zeros(6)
+    wall_b = []
+    for rep in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evb[0].record()
+        csb.run_regions()
+        evb[1].record()
+        csb.run_stage_b()
+        evb[2].record()
+        csb.run_cals()
+        evb[3].record()
+        csb.run_join()
+        evb[4].record()
+        sw.sw_batch_score(ctx, csb.view, SCORING, 0, hits_b)
+        evb[5].record()
+        sw.sw_best_per_read(ctx, csb.view, hits_b, 0, bp, bs)
+        evb[6].record()
+        torch.cuda.synchronize()
+        if rep >= args.warmup:
+            wall_b.append(time.perf_counter() - t0)
+            phase_b += [evb[i].elapsed_time(evb[i + 1]) for i in range(6)]
+    phase_b /= args.steps
+    t_b = float(np.mean(wall_b))
+    _, n_maps = csb.stage_b_maps()
+    mapped_b = n_maps > 0
+    wb_ = csb.windows()
+    mb = b.read_len[wb_["read_id"]].astype(np.int64)
+    nb = np.minimum(wb_["len"].astype(np.int64), len(b.ref) - wb_["ref_begin"].astype(np.int64))
+    with_b = {
+        "ms_per_step": round(t_b * 1e3, 3), "reads_per_s": round(b.n_reads / t_b, 1),
+        "phase_ms": {"regions": round(phase_b[0], 3), "stage_b": round(phase_b[1], 3),
+                     "cal_seeker": round(phase_b[2], 3), "join": round(phase_b[3], 3),
+                     "sw_score": round(phase_b[4], 3), "best": round(phase_b[5], 3)},
+        "mapped_by_stage_b": round(float(mapped_b.mean()), 5),
+        "windows": int(len(wb_)), "cells": int((mb * nb).sum()),
+    }
     return {
         "workload": f"candidate windows found on the device for {b.n_reads} x 100-nt reads "
                     f"(4 Mb GC-40% reference, 1% substitutions, 0.1% indels, 5% random reads): "
@@ -781,6 +822,7 @@ def bench_seeker(ctx, args):
         "origin_is_best_window": round(float(found[real].mean()), 5),
         "mapped_fraction": round(float((bsn >= 250).mean()), 5),
         "random_reads_mapped": int(((bsn >= 250) & ~real).sum()),
+        "with_stage_b": with_b,
     }
 
 

@@ -337,12 +337,47 @@ sw_status sw_seed_regions(sw_ctx *ctx, const sw_batch *reads, const void *d_inde
  * d_cals[r * SW_SEEKER_MAX_CALS ...], ordered by (strand, first), at most
  * SW_SEEKER_MAX_CALS of them (the first in that order), and the remaining
  * slots get invalid CALs {r, 0, 0, 0, 0}: the array is grouped by read, as
- * sw_join_cals takes it.  k is the regions' length. */
+ * sw_join_cals takes it.  k is the regions' length.  d_skip (device, n_reads,
+ * may be NULL): reads with a nonzero entry get invalid CALs only (pass
+ * sw_stage_b's d_n_maps so that the reads stage B mapped skip stages C-E, as
+ * in the paper). */
 #define SW_SEEKER_MAX_CALS 16
 #define SW_SEEKER_MAX_REGIONS 2048
 sw_status sw_cal_seeker(sw_ctx *ctx, const sw_region *d_regions, const uint64_t *d_read_end,
                         uint32_t n_reads, uint64_t cap, uint32_t k, uint32_t merge_gap,
-                        uint32_t min_len, sw_cal *d_cals, void *stream);
+                        uint32_t min_len, const uint32_t *d_skip, sw_cal *d_cals, void *stream);
+
+/* Stage B (Sec. 2, "Stage B: BWT"): whole-read mapping with at most one error,
+ * insertion or deletion.  The paper searches a BWT; here the candidate starts
+ * come from the read's exact seed regions (sw_seed_regions; the first
+ * SW_SEEKER_MAX_REGIONS below cap): every region diagonal d = first - read_pos
+ * gives the starts d - 1, d and d + 1 on its strand.  The query (the read, or
+ * its reverse complement on strand 1; m bases) is verified at each start p, in
+ * this order: exact (ref[p, p + m)), one substitution, one deletion (the
+ * reference holds one base the read lacks after query base i - 1, smallest i
+ * in [1, m - 1]), one insertion (query base i is extra, smallest i in
+ * [1, m - 2]); spans leaving the reference do not apply, nor do indels at the
+ * query's ends.  A read is mapped when a start verifies; only the starts with
+ * the fewest edits are reported, by (strand, start), at most SW_BMAP_MAX:
+ * d_maps[r * SW_BMAP_MAX + j] for j < d_n_maps[r] (the rest zero), 0 records =
+ * unmapped here (the read goes on to the seekers).  `batch` gives the
+ * reference and the reads (the regions' reads); its windows are not used. */
+#define SW_BMAP_MAX 16
+#define SW_BMAP_EXACT 0u
+#define SW_BMAP_SUBST 1u
+#define SW_BMAP_DEL 2u
+#define SW_BMAP_INS 3u
+typedef struct {
+    uint32_t first, last;   /* reference bases of the mapping, inclusive */
+    uint8_t strand;
+    uint8_t edits;          /* 0 or 1 */
+    uint8_t op;             /* SW_BMAP_* */
+    uint8_t reserved;       /* written as 0 */
+    int32_t edit_pos;       /* query position of the edit (i for indels), -1 if exact */
+} sw_bmap;
+sw_status sw_stage_b(sw_ctx *ctx, const sw_batch *batch, const sw_region *d_regions,
+                     const uint64_t *d_read_end, uint64_t cap, sw_bmap *d_maps,
+                     uint32_t *d_n_maps, void *stream);
 
 /* Junction table: caller-owned device arrays d_keys[capacity] (uint64) and
  * d_counts[capacity] (uint32), capacity a power of two in [1, 2^31].  Zero

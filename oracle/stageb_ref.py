@@ -9,7 +9,8 @@ the candidate places come from the exact seed regions of seeker_ref (the
 same index, seeds and repeat cut-off), and each candidate is verified base by
 base.  This module is the plain definition:
 
-Candidates.  For each strand, every region's diagonal d = first - read
+Candidates.  Of the read's regions (seeker_ref.regions order) the first
+MAX_REGIONS count.  For each strand, every region's diagonal d = first - read
 position (the read's first base on the reference if the region lies on an
 error-free stretch) gives the candidate starts d - 1, d and d + 1 (an indel
 before the region shifts its diagonal by one).
@@ -42,6 +43,7 @@ import numpy as np
 from . import seeker_ref as sr
 
 MAX_RECORDS = 16
+MAX_REGIONS = 2048
 EXACT, SUBST, DEL, INS = 0, 1, 2, 3
 
 
@@ -73,7 +75,7 @@ def map_read(read_codes, ref: np.ndarray, index: dict, k: int = sr.K, step: int 
     """Records of one read: [(strand, first, last, edits, op, position)], empty if
     stage B does not map it."""
     q0 = np.asarray(read_codes, dtype=np.uint8)
-    regs = sr.regions(q0, index, k, step, offset, max_occ)
+    regs = sr.regions(q0, index, k, step, offset, max_occ)[:MAX_REGIONS]
     ref = np.asarray(ref, dtype=np.uint8)
     recs = []
     for strand in (0, 1):

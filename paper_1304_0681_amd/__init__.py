@@ -39,6 +39,9 @@ REGION_DTYPE = np.dtype([("first", "<u4"), ("read_pos", "<u2"), ("strand", "u1")
                          ("reserved", "u1")])
 SW_SEEKER_MAX_CALS = 16
 SW_SEEKER_MAX_REGIONS = 2048
+SW_BMAP_MAX = 16
+BMAP_DTYPE = np.dtype([("first", "<u4"), ("last", "<u4"), ("strand", "u1"), ("edits", "u1"),
+                       ("op", "u1"), ("reserved", "u1"), ("edit_pos", "<i4")])
 
 
 class SwError(RuntimeError):
@@ -136,7 +139,8 @@ def lib() -> ctypes.CDLL:
         L.sw_kmer_index_build.argtypes = [P, P, U64, U32, P, U64, P]
         L.sw_seed_regions.argtypes = [P, ctypes.POINTER(sw_batch), P,
                                       ctypes.POINTER(sw_seed_params), P, U64, P, P]
-        L.sw_cal_seeker.argtypes = [P, P, P, U32, U64, U32, U32, U32, P, P]
+        L.sw_cal_seeker.argtypes = [P, P, P, U32, U64, U32, U32, U32, P, P, P]
+        L.sw_stage_b.argtypes = [P, ctypes.POINTER(sw_batch), P, P, U64, P, P, P]
         L.sw_graph_begin.argtypes = [P, P]
         L.sw_graph_end.argtypes = [P, P, ctypes.POINTER(P)]
         L.sw_graph_launch.argtypes = [P, P, P]
@@ -152,7 +156,7 @@ def lib() -> ctypes.CDLL:
                   "sw_mlp_forward", "sw_mlp_grad", "sw_mlp_train_step", "sw_mlp_labels",
                   "sw_filter_candidates", "sw_seed_cals", "sw_join_cals", "sw_junctions_clear",
                   "sw_detect_junctions", "sw_list_junctions", "sw_kmer_index_bytes",
-                  "sw_kmer_index_build", "sw_seed_regions", "sw_cal_seeker"):
+                  "sw_kmer_index_build", "sw_seed_regions", "sw_cal_seeker", "sw_stage_b"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -397,10 +401,15 @@ def sw_seed_regions(ctx, batch, d_index, params, d_regions, cap, d_read_end, str
 
 
 def sw_cal_seeker(ctx, d_regions, d_read_end, n_reads, cap, k, merge_gap, min_len, d_cals,
-                  stream=None):
+                  stream=None, d_skip=None):
     _check(ctx, lib().sw_cal_seeker(ctx, _ptr(d_regions), _ptr(d_read_end), int(n_reads), int(cap),
-                                    int(k), int(merge_gap), int(min_len), _ptr(d_cals),
-                                    _stream_ptr(stream)))
+                                    int(k), int(merge_gap), int(min_len), _ptr(d_skip),
+                                    _ptr(d_cals), _stream_ptr(stream)))
+
+
+def sw_stage_b(ctx, batch, d_regions, d_read_end, cap, d_maps, d_n_maps, stream=None):
+    _check(ctx, lib().sw_stage_b(ctx, ctypes.byref(batch.c), _ptr(d_regions), _ptr(d_read_end),
+                                 int(cap), _ptr(d_maps), _ptr(d_n_maps), _stream_ptr(stream)))
 
 
 def sw_graph_begin(ctx, stream):

@@ -1754,7 +1754,7 @@ sw_status sw_seed_regions(sw_ctx *ctx, const sw_batch *reads, const void *d_inde
 
 sw_status sw_cal_seeker(sw_ctx *ctx, const sw_region *d_regions, const uint64_t *d_read_end,
                         uint32_t n_reads, uint64_t cap, uint32_t k, uint32_t merge_gap,
-                        uint32_t min_len, sw_cal *d_cals, void *stream)
+                        uint32_t min_len, const uint32_t *d_skip, sw_cal *d_cals, void *stream)
 {
     if (!ctx)
         return fail(nullptr, SW_E_INVALID, "ctx is NULL");
@@ -1765,8 +1765,29 @@ sw_status sw_cal_seeker(sw_ctx *ctx, const sw_region *d_regions, const uint64_t 
     if (k < 1 || k > 65535)
         return fail(ctx, SW_E_RANGE, "region length out of range");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    HIP_TRY(ctx, launch_cal_seek(d_regions, d_read_end, n_reads, cap, k, merge_gap, min_len, d_cals,
-                                 static_cast<hipStream_t>(stream)));
+    HIP_TRY(ctx, launch_cal_seek(d_regions, d_read_end, n_reads, cap, k, merge_gap, min_len, d_skip,
+                                 d_cals, static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_stage_b(sw_ctx *ctx, const sw_batch *b, const sw_region *d_regions,
+                     const uint64_t *d_read_end, uint64_t cap, sw_bmap *d_maps, uint32_t *d_n_maps,
+                     void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    if (!b)
+        return fail(ctx, SW_E_INVALID, "batch is NULL");
+    if (b->n_reads == 0)
+        return SW_OK;
+    if (!b->d_read_len || !b->d_read_off || !b->d_reads2b || !b->d_ref2b || !d_read_end ||
+        !d_maps || !d_n_maps || (cap && !d_regions))
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    if (b->ref_len > (1ull << 32))
+        return fail(ctx, SW_E_RANGE, "reference longer than 2^32 bases");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_stage_b(*b, d_regions, d_read_end, cap, d_maps, d_n_maps,
+                                static_cast<hipStream_t>(stream)));
     return SW_OK;
 }
 

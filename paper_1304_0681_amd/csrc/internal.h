@@ -153,6 +153,8 @@ hipError_t launch_regions(const sw_batch &b, const uint32_t *starts, const uint3
                           uint32_t *cnt, uint64_t *read_end, uint64_t *tsum, hipStream_t st);
 hipError_t launch_cal_seek(const sw_region *reg, const uint64_t *read_end, uint32_t n_reads,
                            uint64_t cap, uint32_t k, uint32_t merge_gap, uint32_t min_len,
-                           sw_cal *cals, hipStream_t st);
+                           const uint32_t *skip, sw_cal *cals, hipStream_t st);
+hipError_t launch_stage_b(const sw_batch &b, const sw_region *reg, const uint64_t *read_end,
+                          uint64_t cap, sw_bmap *maps, uint32_t *n_maps, hipStream_t st);
 
 }  // namespace hpgsw

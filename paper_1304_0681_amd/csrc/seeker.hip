@@ -272,6 +272,34 @@ __global__ void __launch_bounds__(256) k_region_write(const SeedParams P, const 
     }
 }
 
+// LDS writes of the wave visible to all its lanes
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Bitonic sort of keys[0, P2) (P2 a power of two) by one wave, ascending.
+__device__ void sort_keys(uint64_t *keys, uint32_t P2, int lane)
+{
+    for (uint32_t size = 2; size <= P2; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t i = lane; i < P2; i += 64) {
+                const uint32_t j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const uint64_t x = keys[i], y = keys[j];
+                    if ((x > y) == up) {
+                        keys[i] = y;
+                        keys[j] = x;
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // CAL seeker: one wave per read.  Its first kMaxRegions regions are sorted in
 // LDS by (strand, first) (bitonic sort), then the first lane merges them and
@@ -283,7 +311,8 @@ __global__ void __launch_bounds__(64 * kSeekWaves) k_cal_seek(const sw_region *r
                                                               const uint64_t *read_end,
                                                               uint32_t n_reads, uint64_t cap,
                                                               uint32_t k, uint32_t merge_gap,
-                                                              uint32_t min_len, sw_cal *cals)
+                                                              uint32_t min_len, const uint32_t *skip,
+                                                              sw_cal *cals)
 {
     __shared__ uint64_t keys_all[kSeekWaves][kMaxRegions];
     const uint32_t wave = threadIdx.x >> 6;
@@ -294,7 +323,9 @@ __global__ void __launch_bounds__(64 * kSeekWaves) k_cal_seek(const sw_region *r
         const uint64_t b = r ? read_end[r - 1] : 0ull;
         uint64_t e = read_end[r];
         if (e > cap) e = cap;
-        const uint32_t n = e > b ? (uint32_t)min(e - b, (uint64_t)kMaxRegions) : 0u;
+        uint32_t n = e > b ? (uint32_t)min(e - b, (uint64_t)kMaxRegions) : 0u;
+        if (skip && skip[r])
+            n = 0;
         uint32_t P2 = 1;
         while (P2 < n) P2 <<= 1;
         for (uint32_t i = lane; i < P2; i += 64) {
@@ -305,25 +336,8 @@ __global__ void __launch_bounds__(64 * kSeekWaves) k_cal_seek(const sw_region *r
             }
             keys[i] = key;
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        for (uint32_t size = 2; size <= P2; size <<= 1) {
-            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t i = lane; i < P2; i += 64) {
-                    const uint32_t j = i ^ stride;
-                    if (j > i) {
-                        const bool up = (i & size) == 0;
-                        const uint64_t x = keys[i], y = keys[j];
-                        if ((x > y) == up) {
-                            keys[i] = y;
-                            keys[j] = x;
-                        }
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-            }
-        }
+        wave_sync();
+        sort_keys(keys, P2, lane);
         if (lane == 0) {
             sw_cal *out = cals + r * (uint64_t)kCals;
             int nc = 0;
@@ -350,8 +364,169 @@ __global__ void __launch_bounds__(64 * kSeekWaves) k_cal_seek(const sw_region *r
             for (int j = nc; j < kCals; ++j)
                 out[j] = sw_cal{(uint32_t)r, 0u, 0u, 0u, 0u, 0u};
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stage B: whole-read mapping with at most one edit.  One wave per read: the
+// diagonals of its first kMaxRegions regions are sorted in LDS; walking them in
+// (strand, diagonal) order, every candidate start d - 1, d, d + 1 not seen
+// before is verified by the whole wave (lane j compares query base j with the
+// reference on the candidate's diagonal and its two neighbours, ballots give
+// the mismatch positions), and the records of the fewest edits are kept.
+// ---------------------------------------------------------------------------
+constexpr int kBWaves = 2;
+constexpr int kBMax = SW_BMAP_MAX;
+
+struct StageBParams {
+    const uint32_t *reads;
+    uint64_t read_words;
+    const uint64_t *read_off;
+    const uint16_t *read_len;
+    uint32_t n_reads;
+    uint64_t reads_len;
+    const uint32_t *ref;
+    uint64_t ref_len;
+    const sw_region *reg;
+    const uint64_t *read_end;
+    uint64_t cap;
+    sw_bmap *maps;
+    uint32_t *n_maps;
+};
+
+__device__ __forceinline__ uint32_t base_of(const uint32_t *seq, uint64_t p)
+{
+    return (seq[p >> 4] >> (2u * (uint32_t)(p & 15))) & 3u;
+}
+
+struct Verdict {
+    int e;             // 0, 1, or 2 (no mapping at this start)
+    int op;
+    int pos;
+    uint64_t last;
+};
+
+// The query at start p of strand s, by the whole wave (every lane returns it).
+__device__ Verdict verify_start(const StageBParams &P, uint64_t off, uint32_t m, uint32_t s,
+                                int64_t p, int lane)
+{
+    const uint64_t L = P.ref_len;
+    int cnt0 = 0, f0 = (int)m, lp = -1, lm = -1;
+    for (uint32_t j0 = 0; j0 < m; j0 += 64) {
+        const uint32_t j = j0 + (uint32_t)lane;
+        const bool valid = j < m;
+        uint32_t qb = 0;
+        if (valid)
+            qb = s ? 3u - base_of(P.reads, off + (m - 1 - j)) : base_of(P.reads, off + j);
+        const uint64_t x0 = (uint64_t)p + j;
+        const uint32_t r0 = valid && x0 < L ? base_of(P.ref, x0) : 4u;
+        const uint32_t rp = valid && x0 + 1 < L ? base_of(P.ref, x0 + 1) : 4u;
+        const uint32_t rm = valid && j >= 1 && x0 - 1 < L ? base_of(P.ref, x0 - 1) : 4u;
+        const uint64_t m0 = __ballot(valid && qb != r0);
+        const uint64_t mp = __ballot(valid && j >= 1 && qb != rp);
+        const uint64_t mm = __ballot(valid && j >= 2 && qb != rm);
+        cnt0 += __popcll(m0);
+        if (f0 == (int)m && m0)
+            f0 = (int)j0 + __ffsll((long long)m0) - 1;
+        if (mp)
+            lp = (int)j0 + 63 - __clzll((long long)mp);
+        if (mm)
+            lm = (int)j0 + 63 - __clzll((long long)mm);
+    }
+    const uint64_t pu = (uint64_t)p;
+    if (pu + m <= L) {
+        if (cnt0 == 0)
+            return Verdict{0, SW_BMAP_EXACT, -1, pu + m - 1};
+        if (cnt0 == 1)
+            return Verdict{1, SW_BMAP_SUBST, f0, pu + m - 1};
+    }
+    if (pu + m + 1 <= L && m >= 2) {
+        const int i = max(1, lp + 1);
+        if (i <= (int)m - 1 && i <= f0)
+            return Verdict{1, SW_BMAP_DEL, i, pu + m};
+    }
+    if (pu + m - 1 <= L && m >= 3) {
+        const int i = max(1, lm);
+        if (i <= (int)m - 2 && i <= f0)
+            return Verdict{1, SW_BMAP_INS, i, pu + m - 2};
+    }
+    return Verdict{2, 0, 0, 0};
+}
+
+__global__ void __launch_bounds__(64 * kBWaves) k_stage_b(const StageBParams P)
+{
+    __shared__ uint64_t keys_all[kBWaves][kMaxRegions];
+    const uint32_t wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    uint64_t *keys = keys_all[wave];
+    for (uint64_t r = (uint64_t)blockIdx.x * kBWaves + wave; r < P.n_reads;
+         r += (uint64_t)gridDim.x * kBWaves) {
+        const uint32_t m = P.read_len[r];
+        const uint64_t off = P.read_off[r];
+        const uint64_t b = r ? P.read_end[r - 1] : 0ull;
+        uint64_t e = P.read_end[r];
+        if (e > P.cap) e = P.cap;
+        uint32_t n = e > b ? (uint32_t)min(e - b, (uint64_t)kMaxRegions) : 0u;
+        if (off + m > P.reads_len)
+            n = 0;
+        uint32_t P2 = 1;
+        while (P2 < n) P2 <<= 1;
+        for (uint32_t i = lane; i < P2; i += 64) {
+            uint64_t key = ~0ull;
+            if (i < n) {
+                const sw_region g = P.reg[b + i];
+                const int64_t d = (int64_t)g.first - (int64_t)g.read_pos + 65536;
+                key = ((uint64_t)(g.strand ? 1 : 0) << 48) | (uint64_t)d;
+            }
+            keys[i] = key;
+        }
+        wave_sync();
+        sort_keys(keys, P2, lane);
+        sw_bmap *out = P.maps + r * (uint64_t)kBMax;
+        int best = 2, cnt = 0;
+        uint64_t prev = ~0ull;
+        uint32_t last_s = 2;
+        int64_t last_p = INT64_MIN;
+        for (uint32_t i = 0; i < n; ++i) {
+            const uint64_t key = keys[i];
+            if (key == prev)
+                continue;
+            prev = key;
+            const uint32_t s = (uint32_t)(key >> 48);
+            const int64_t d = (int64_t)(key & ((1ull << 48) - 1)) - 65536;
+            if (s != last_s) {
+                last_s = s;
+                last_p = INT64_MIN;
+            }
+            for (int t = -1; t <= 1; ++t) {
+                const int64_t p = d + t;
+                if (p <= last_p)
+                    continue;
+                last_p = p;
+                if (p < 0)
+                    continue;
+                const Verdict v = verify_start(P, off, m, s, p, lane);
+                if (v.e > 1)
+                    continue;
+                if (v.e < best) {
+                    best = v.e;
+                    cnt = 0;
+                }
+                if (v.e == best && cnt < kBMax) {
+                    if (lane == 0)
+                        out[cnt] = sw_bmap{(uint32_t)p, (uint32_t)v.last, (uint8_t)s, (uint8_t)v.e,
+                                           (uint8_t)v.op, 0u, v.pos};
+                    ++cnt;
+                }
+            }
+        }
+        for (int j = lane; j < kBMax; j += 64)
+            if (j >= cnt)
+                out[j] = sw_bmap{0u, 0u, 0u, 0u, 0u, 0u, 0};
+        if (lane == 0)
+            P.n_maps[r] = (uint32_t)cnt;
+        wave_sync();
     }
 }
 
@@ -425,14 +600,39 @@ hipError_t launch_regions(const sw_batch &b, const uint32_t *starts, const uint3
 
 hipError_t launch_cal_seek(const sw_region *reg, const uint64_t *read_end, uint32_t n_reads,
                            uint64_t cap, uint32_t k, uint32_t merge_gap, uint32_t min_len,
-                           sw_cal *cals, hipStream_t st)
+                           const uint32_t *skip, sw_cal *cals, hipStream_t st)
 {
     if (n_reads == 0)
         return hipSuccess;
     uint64_t blocks = (n_reads + kSeekWaves - 1) / kSeekWaves;
     if (blocks > 65535) blocks = 65535;
     hipLaunchKernelGGL(k_cal_seek, dim3((unsigned)blocks), dim3(64 * kSeekWaves), 0, st, reg,
-                       read_end, n_reads, cap, k, merge_gap, min_len, cals);
+                       read_end, n_reads, cap, k, merge_gap, min_len, skip, cals);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_b(const sw_batch &b, const sw_region *reg, const uint64_t *read_end,
+                          uint64_t cap, sw_bmap *maps, uint32_t *n_maps, hipStream_t st)
+{
+    if (b.n_reads == 0)
+        return hipSuccess;
+    StageBParams P;
+    P.reads = b.d_reads2b;
+    P.read_words = (b.reads_len + 15) / 16;
+    P.read_off = b.d_read_off;
+    P.read_len = b.d_read_len;
+    P.n_reads = b.n_reads;
+    P.reads_len = b.reads_len;
+    P.ref = b.d_ref2b;
+    P.ref_len = b.ref_len;
+    P.reg = reg;
+    P.read_end = read_end;
+    P.cap = cap;
+    P.maps = maps;
+    P.n_maps = n_maps;
+    uint64_t blocks = (b.n_reads + kBWaves - 1) / kBWaves;
+    if (blocks > 65535) blocks = 65535;
+    hipLaunchKernelGGL(k_stage_b, dim3((unsigned)blocks), dim3(64 * kBWaves), 0, st, P);
     return hipGetLastError();
 }
 

@@ -10,6 +10,11 @@ joined windows with fixed device buffers and no host round trip:
   sw_cal_seeker     each read's regions merged into CALs
   sw_join_cals      CALs extended and joined into windows
 
+With stage_b=True the whole-read mapping of stage B (sw_stage_b, at most one
+edit, from the same regions) runs between the two seekers, and the reads it
+maps get no CALs: as in the paper, only the reads stage B cannot map go on to
+stages C-E.
+
 The windows come back as a batch view (`view`) whose pair count stays on the
 device, ready for sw_batch_score / sw_best_per_read / sw_batch_traceback.
 """
@@ -17,8 +22,9 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (REGION_DTYPE, SW_SEEKER_MAX_CALS, WINDOW_DTYPE, DeviceBatch, sw_cal_seeker,
-               sw_join_cals, sw_kmer_index_build, sw_kmer_index_bytes, sw_seed_regions)
+from . import (BMAP_DTYPE, REGION_DTYPE, SW_BMAP_MAX, SW_SEEKER_MAX_CALS, WINDOW_DTYPE,
+               DeviceBatch, sw_cal_seeker, sw_join_cals, sw_kmer_index_build, sw_kmer_index_bytes,
+               sw_seed_regions, sw_stage_b)
 
 K, STEP, OFFSET, MAX_OCC = 15, 12, 7, 64
 
@@ -52,7 +58,7 @@ class CandidateSeeker:
     def __init__(self, ctx, db: DeviceBatch, index: KmerIndex, step: int = STEP,
                  offset: int = OFFSET, max_occ: int = MAX_OCC, merge_gap: int = 50,
                  min_len: int = 20, ext: int = 30, max_gap: int = 5000,
-                 region_cap: int | None = None):
+                 region_cap: int | None = None, stage_b: bool = False):
         import torch
         self.ctx, self.db, self.index = ctx, db, index
         self.params = (index.k, int(step), int(offset), int(max_occ))
@@ -69,14 +75,24 @@ class CandidateSeeker:
         self.win = torch.empty(max(self.n_cals, 1) * 12, dtype=torch.uint8, device=dev)
         self.n_win = torch.zeros(1, dtype=torch.int32, device=dev)
         self.view = db.view(self.win, max(self.n_cals, 1), self.n_win)
+        self.stage_b = bool(stage_b)
+        self.maps = self.n_maps = None
+        if self.stage_b:
+            self.maps = torch.empty(max(n, 1) * SW_BMAP_MAX * 16, dtype=torch.uint8, device=dev)
+            self.n_maps = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
 
     def run_regions(self, stream=None):
         sw_seed_regions(self.ctx, self.db, self.index.buf, self.params, self.regions, self.cap,
                         self.read_end, stream)
 
+    def run_stage_b(self, stream=None):
+        sw_stage_b(self.ctx, self.db, self.regions, self.read_end, self.cap, self.maps,
+                   self.n_maps, stream)
+
     def run_cals(self, stream=None):
         sw_cal_seeker(self.ctx, self.regions, self.read_end, self.n_reads, self.cap, self.index.k,
-                      self.merge_gap, self.min_len, self.cals, stream)
+                      self.merge_gap, self.min_len, self.cals, stream,
+                      d_skip=self.n_maps if self.stage_b else None)
 
     def run_join(self, stream=None):
         sw_join_cals(self.ctx, self.cals, self.n_cals, self.n_reads, self.db.ref_len, self.ext,
@@ -84,8 +100,16 @@ class CandidateSeeker:
 
     def run(self, stream=None):
         self.run_regions(stream)
+        if self.stage_b:
+            self.run_stage_b(stream)
         self.run_cals(stream)
         self.run_join(stream)
+
+    def stage_b_maps(self):
+        """(records[n_reads, SW_BMAP_MAX], counts) of the last run (host copies)."""
+        n = self.n_reads
+        recs = self.maps.cpu().numpy().view(BMAP_DTYPE)[:n * SW_BMAP_MAX].reshape(n, SW_BMAP_MAX)
+        return recs.copy(), self.n_maps.cpu().numpy().view(np.uint32)[:n].copy()
 
     def region_list(self):
         """(regions, read_end) of the last run (host copies)."""

@@ -59,6 +59,10 @@ int model_sbfe(int src, int offset, int width);
 inline void __threadfence_block() {}
 void __syncthreads();
 void model_wave_barrier();
+uint64_t __ballot(int pred);
+inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
+inline int __ffsll(long long x) { return __builtin_ffsll(x); }
+inline int __clzll(long long x) { return x ? __builtin_clzll((unsigned long long)x) : 64; }
 #define __builtin_amdgcn_wave_barrier model_wave_barrier
 #define __builtin_amdgcn_fence(...) __atomic_thread_fence(__ATOMIC_SEQ_CST)
 

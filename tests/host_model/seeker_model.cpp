@@ -44,6 +44,7 @@ struct SpinBarrier {
 };
 
 thread_local SpinBarrier *t_block, *t_wave;
+thread_local uint64_t *t_ballot;   // the wave's ballot word
 
 // Every block of a launch of `fn` with `block` threads, one block at a time.
 template <class F> void launch(unsigned grid, unsigned block, F fn)
@@ -53,6 +54,7 @@ template <class F> void launch(unsigned grid, unsigned block, F fn)
         std::vector<std::unique_ptr<SpinBarrier>> wb;
         for (unsigned w = 0; w < (block + 63) / 64; ++w)
             wb.emplace_back(new SpinBarrier((int)std::min(64u, block - 64 * w)));
+        std::vector<uint64_t> ballots((block + 63) / 64, 0);
         std::vector<std::thread> th;
         for (unsigned t = 0; t < block; ++t)
             th.emplace_back([&, t]() {
@@ -62,6 +64,7 @@ template <class F> void launch(unsigned grid, unsigned block, F fn)
                 blockDim = ModelIdx{block, 1, 1};
                 t_block = &bb;
                 t_wave = wb[t / 64].get();
+                t_ballot = &ballots[t / 64];
                 fn();
             });
         for (auto &x : th)
@@ -106,6 +109,22 @@ template <class T> void scan(const uint32_t *in, uint64_t n, T *out, bool at_end
 }  // namespace
 
 void __syncthreads() { t_block->arrive_and_wait(); }
+
+// every lane sets its bit, the wave meets, reads the word, meets again, and the
+// last lane out clears it for the next ballot
+uint64_t __ballot(int pred)
+{
+    const unsigned lane = threadIdx.x & 63u;
+    if (pred)
+        __atomic_fetch_or(t_ballot, 1ull << lane, __ATOMIC_SEQ_CST);
+    t_wave->arrive_and_wait();
+    const uint64_t v = __atomic_load_n(t_ballot, __ATOMIC_SEQ_CST);
+    t_wave->arrive_and_wait();
+    if (lane == 0)
+        __atomic_store_n(t_ballot, 0ull, __ATOMIC_SEQ_CST);
+    t_wave->arrive_and_wait();
+    return v;
+}
 void model_wave_barrier() { t_wave->arrive_and_wait(); }
 uint32_t atomicAdd(uint32_t *p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 uint32_t atomicSub(uint32_t *p, uint32_t v) { return __atomic_fetch_sub(p, v, __ATOMIC_SEQ_CST); }
@@ -180,16 +199,48 @@ void model_regions(int at_end, const uint32_t *reads2b, uint64_t reads_len, cons
 
 void model_cal_seek(int at_end, const sw_region *reg, uint64_t n_reg, const uint64_t *read_end,
                     uint32_t n_reads, uint64_t cap, uint32_t k, uint32_t merge_gap, uint32_t min_len,
-                    sw_cal *cals_out, unsigned blocks)
+                    const uint32_t *skip, sw_cal *cals_out, unsigned blocks)
 {
     Guarded g_reg(reg, sizeof(sw_region) * n_reg, at_end), g_end(read_end, 8ull * n_reads, at_end);
     Guarded g_cals(nullptr, sizeof(sw_cal) * hpgsw::kCals * n_reads, at_end);
+    Guarded g_skip(skip, skip ? 4ull * n_reads : 0, at_end);
     const sw_region *R = g_reg.as<sw_region>();
     const uint64_t *E = g_end.as<uint64_t>();
+    const uint32_t *K = skip ? g_skip.as<uint32_t>() : nullptr;
     sw_cal *C = g_cals.as<sw_cal>();
     launch(blocks, 64 * hpgsw::kSeekWaves,
-           [&] { hpgsw::k_cal_seek(R, E, n_reads, cap, k, merge_gap, min_len, C); });
+           [&] { hpgsw::k_cal_seek(R, E, n_reads, cap, k, merge_gap, min_len, K, C); });
     memcpy(cals_out, C, sizeof(sw_cal) * hpgsw::kCals * n_reads);
+}
+
+void model_stage_b(int at_end, const uint32_t *reads2b, uint64_t reads_len, const uint64_t *read_off,
+                   const uint16_t *read_len, uint32_t n_reads, const uint32_t *ref2b,
+                   uint64_t ref_len, const sw_region *reg, uint64_t n_reg, const uint64_t *read_end,
+                   uint64_t cap, sw_bmap *maps_out, uint32_t *n_maps_out, unsigned blocks)
+{
+    const uint64_t read_words = (reads_len + 15) / 16, ref_words = (ref_len + 15) / 16;
+    Guarded g_reads(reads2b, 4 * read_words, at_end), g_off(read_off, 8ull * n_reads, at_end);
+    Guarded g_len(read_len, 2ull * n_reads, at_end), g_ref(ref2b, 4 * ref_words, at_end);
+    Guarded g_reg(reg, sizeof(sw_region) * n_reg, at_end), g_end(read_end, 8ull * n_reads, at_end);
+    Guarded g_maps(nullptr, sizeof(sw_bmap) * hpgsw::kBMax * n_reads, at_end);
+    Guarded g_n(nullptr, 4ull * n_reads, at_end);
+    hpgsw::StageBParams P;
+    P.reads = g_reads.as<uint32_t>();
+    P.read_words = read_words;
+    P.read_off = g_off.as<uint64_t>();
+    P.read_len = g_len.as<uint16_t>();
+    P.n_reads = n_reads;
+    P.reads_len = reads_len;
+    P.ref = g_ref.as<uint32_t>();
+    P.ref_len = ref_len;
+    P.reg = g_reg.as<sw_region>();
+    P.read_end = g_end.as<uint64_t>();
+    P.cap = cap;
+    P.maps = g_maps.as<sw_bmap>();
+    P.n_maps = g_n.as<uint32_t>();
+    launch(blocks, 64 * hpgsw::kBWaves, [&] { hpgsw::k_stage_b(P); });
+    memcpy(maps_out, P.maps, sizeof(sw_bmap) * hpgsw::kBMax * n_reads);
+    memcpy(n_maps_out, P.n_maps, 4ull * n_reads);
 }
 
 }  // extern "C"

@@ -51,3 +51,30 @@ def reads_from(seed: int, ref: np.ndarray, n_reads: int, p_sub: float = 0.02):
         origins.append(o)
         strands.append(st)
     return reads, np.array(origins), np.array(strands)
+
+
+def one_edit_reads(seed: int, ref: np.ndarray, n_reads: int, m: int = 100):
+    """Reads at most one edit away from the reference: exact copies, one
+    substitution, one deleted or one inserted base at an interior position,
+    on either strand, some at the very start or end of the reference."""
+    g = np.random.default_rng(seed)
+    L = len(ref)
+    reads = []
+    for r in range(n_reads):
+        kind = r % 4
+        u = g.random()
+        o = 0 if u < 0.05 else (L - m - 1 if u < 0.1 else int(g.integers(0, L - m - 2)))
+        if kind == 0:
+            q = ref[o:o + m].copy()
+        elif kind == 1:
+            q = ref[o:o + m].copy()
+            j = int(g.integers(0, m))
+            q[j] = (q[j] + int(g.integers(1, 4))) % 4
+        elif kind == 2:
+            q = np.delete(ref[o:o + m + 1], int(g.integers(1, m)))
+        else:
+            q = np.insert(ref[o:o + m - 1], int(g.integers(1, m - 1)), int(g.integers(0, 4)))
+        if g.random() < 0.5:
+            q = (3 - q[::-1]).astype(np.uint8)
+        reads.append(q.astype(np.uint8))
+    return reads

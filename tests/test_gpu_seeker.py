@@ -149,3 +149,40 @@ def test_found_windows_hold_the_origins(ctx, seeded):
                        >= 0.5 * lens[r] for x in by_read.get(r, []))
         mapped += bsn[r] >= 2 * lens[r]
     assert covered >= 0.995 * n and mapped >= 0.97 * n, (covered, mapped, n)
+
+
+def test_stage_b_exact_and_skip(ctx):
+    """Stage B on reads one edit or less from the reference (both strands, at
+    the reference ends) and on mutated and random reads: every read's records
+    equal the oracle's, and the CAL seeker then leaves the mapped reads out."""
+    from oracle import stageb_ref as sb
+    from seeker_inputs import one_edit_reads
+    ref = reference_with_repeats(65, 800_000, families=10, copies=(2, 8))
+    reads = one_edit_reads(66, ref, 3000) + reads_from(67, ref, 3000)[0]
+    db = _db(ctx, ref, reads)
+    idx = KmerIndex(ctx, db.ref2b, db.ref_len, k=15)
+    cs = CandidateSeeker(ctx, db, idx, max_occ=40, stage_b=True)
+    cs.run()
+    torch.cuda.synchronize()
+    recs, n_maps = cs.stage_b_maps()
+    oidx = sr.build_index_fast(ref, 15)
+    kinds = set()
+    for r, q in enumerate(reads):
+        want = sb.map_read(q, ref, oidx, 15, 12, 7, 40)
+        n = int(n_maps[r])
+        got = [(int(x["strand"]), int(x["first"]), int(x["last"]), int(x["edits"]), int(x["op"]),
+                int(x["edit_pos"])) for x in recs[r, :n]]
+        assert got == want, r
+        assert (recs[r, n:]["first"] == 0).all() and (recs[r, n:]["edit_pos"] == 0).all()
+        kinds |= {w[4] for w in want}
+    assert kinds == {sb.EXACT, sb.SUBST, sb.DEL, sb.INS}
+    assert (n_maps[:3000] > 0).mean() > 0.97
+    got = cs.cals.cpu().numpy().view(jr_dtype())
+    for r in range(len(reads)):
+        row = got[r * sw.SW_SEEKER_MAX_CALS:(r + 1) * sw.SW_SEEKER_MAX_CALS]
+        if n_maps[r]:
+            assert not row["valid"].any()
+        else:
+            want = sr.cals(r, sr.regions(reads[r], oidx, 15, 12, 7, 40), 50, 20)
+            assert [(int(c["read_id"]), int(c["first"]), int(c["last"]), int(c["strand"]), 1)
+                    for c in row if c["valid"]] == want

@@ -18,7 +18,8 @@ import pytest
 import oracle
 import synth
 from oracle import seeker_ref as sr
-from seeker_inputs import reads_from, reference_with_repeats
+from oracle import stageb_ref as sb
+from seeker_inputs import one_edit_reads, reads_from, reference_with_repeats
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HM = os.path.join(ROOT, "tests", "host_model")
@@ -27,6 +28,9 @@ REGION_DTYPE = np.dtype([("first", "<u4"), ("read_pos", "<u2"), ("strand", "u1")
 CAL_DTYPE = np.dtype([("read_id", "<u4"), ("first", "<u4"), ("last", "<u4"), ("strand", "u1"),
                       ("valid", "u1"), ("reserved", "<u2")])
 N_CALS = 16
+BMAP_DTYPE = np.dtype([("first", "<u4"), ("last", "<u4"), ("strand", "u1"), ("edits", "u1"),
+                       ("op", "u1"), ("reserved", "u1"), ("edit_pos", "<i4")])
+N_MAPS = 16
 
 
 @pytest.fixture(scope="module")
@@ -136,7 +140,7 @@ def test_cal_seek(model, merge_gap, min_len, at_end):
     regs, end = _regions(model, reads, starts, pos, k, step, offset, max_occ, 10**6, 1)
     cals = np.zeros(len(reads) * N_CALS, CAL_DTYPE)
     model.model_cal_seek(at_end, _p(regs), ctypes.c_uint64(len(regs)), _p(end), len(reads),
-                         ctypes.c_uint64(len(regs)), k, merge_gap, min_len, _p(cals), 3)
+                         ctypes.c_uint64(len(regs)), k, merge_gap, min_len, None, _p(cals), 3)
     got = _cal_rows(cals, len(reads))
     idx = sr.build_index_fast(ref, k)
     n = 0
@@ -164,7 +168,7 @@ def test_cal_seek_caps(model):
     for cap in (len(regs), ends[3] + 100):
         cals = np.zeros(6 * N_CALS, CAL_DTYPE)
         model.model_cal_seek(1, _p(regs), ctypes.c_uint64(len(regs)), _p(end), 6,
-                             ctypes.c_uint64(cap), k, 30, 10, _p(cals), 2)
+                             ctypes.c_uint64(cap), k, 30, 10, None, _p(cals), 2)
         got = _cal_rows(cals, 6)
         b = 0
         for r in range(6):
@@ -174,3 +178,43 @@ def test_cal_seek_caps(model):
             assert got[r] == sr.cals(r, reg_r, 30, 10), (cap, r)
             b = ends[r]
     assert len(got[3]) == N_CALS
+
+
+@pytest.mark.parametrize("at_end", [1, 0])
+def test_stage_b(model, at_end):
+    """Whole-read mapping with at most one edit: every read's records (fewest
+    edits, by strand and start) equal the oracle's; reads with more edits and
+    random reads get none; the skip mask empties their CAL slots."""
+    k, step, offset, max_occ = 10, 12, 7, 6
+    ref = reference_with_repeats(44, 60_000, families=3, copies=(2, 9))
+    starts, pos = _index(model, ref, k, 1)
+    reads = one_edit_reads(45, ref, 240) + reads_from(46, ref, 160)[0]
+    regs, end = _regions(model, reads, starts, pos, k, step, offset, max_occ, 10**6, 1)
+    r2b, rl, off, lens = _reads_arrays(reads)
+    maps = np.zeros(len(reads) * N_MAPS, BMAP_DTYPE)
+    n_maps = np.zeros(len(reads), np.uint32)
+    model.model_stage_b(at_end, _p(r2b), ctypes.c_uint64(rl), _p(off), _p(lens), len(reads),
+                        _p(_pack(ref)), ctypes.c_uint64(len(ref)), _p(regs),
+                        ctypes.c_uint64(len(regs)), _p(end), ctypes.c_uint64(len(regs)), _p(maps),
+                        _p(n_maps), 3)
+    idx = sr.build_index_fast(ref, k)
+    kinds = set()
+    for r, q in enumerate(reads):
+        want = sb.map_read(q, ref, idx, k, step, offset, max_occ)
+        row = maps[r * N_MAPS:(r + 1) * N_MAPS]
+        n = int(n_maps[r])
+        got = [(int(x["strand"]), int(x["first"]), int(x["last"]), int(x["edits"]), int(x["op"]),
+                int(x["edit_pos"])) for x in row[:n]]
+        assert got == want, r
+        assert (row[n:] == np.zeros(1, BMAP_DTYPE)).all()
+        kinds |= {w[4] for w in want}
+    assert kinds == {sb.EXACT, sb.SUBST, sb.DEL, sb.INS}
+    assert (n_maps[:240] > 0).mean() > 0.95
+    # reads stage B mapped get no CALs
+    cals = np.zeros(len(reads) * N_CALS, CAL_DTYPE)
+    model.model_cal_seek(at_end, _p(regs), ctypes.c_uint64(len(regs)), _p(end), len(reads),
+                         ctypes.c_uint64(len(regs)), k, 50, 20, _p(n_maps), _p(cals), 2)
+    got = _cal_rows(cals, len(reads))
+    for r, q in enumerate(reads):
+        want = [] if n_maps[r] else sr.cals(r, sr.regions(q, idx, k, step, offset, max_occ), 50, 20)
+        assert got[r] == want
