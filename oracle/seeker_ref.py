@@ -2,7 +2,7 @@
 imported by tests, never by the product path).
 
 Stage C of the paper (Sec. 2, "Stage C: Region Seeker") cuts a read into short
-overlapping seeds (15 nt, "tentatively"), in two phases: one series of seeds
+overlapping seeds (15 nt, as a provisional choice), in two phases: one series of seeds
 from the read's first base and a second series from its eighth, so that a
 100-nt read gives 8 + 7 seeds.  Every seed is mapped exactly (no errors) onto
 the reference; each place it matches is a region.  Stage D ("Stage D: CAL

@@ -407,33 +407,67 @@ struct Verdict {
     uint64_t last;
 };
 
-// The query at start p of strand s, by the whole wave (every lane returns it).
-__device__ Verdict verify_start(const StageBParams &P, uint64_t off, uint32_t m, uint32_t s,
-                                int64_t p, int lane)
+// Mismatches of the query (strand s) against the reference on the diagonals
+// d - 2 .. d + 2 (index o + 2 for diagonal d + o): their number over the query
+// and the first and last mismatching query position (m and -1 if none).  One
+// pass of the whole wave: lane j compares query base j with the five
+// reference bases it faces, read from one 64-bit window of the packed words;
+// positions outside the reference count as mismatches.
+struct DiagStats {
+    int cnt[5], first[5], last[5];
+};
+
+__device__ DiagStats scan_diagonals(const StageBParams &P, uint64_t off, uint32_t m, uint32_t s,
+                                    int64_t d, int lane)
 {
-    const uint64_t L = P.ref_len;
-    int cnt0 = 0, f0 = (int)m, lp = -1, lm = -1;
+    DiagStats S;
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+        S.cnt[o] = 0;
+        S.first[o] = (int)m;
+        S.last[o] = -1;
+    }
+    const int64_t L = (int64_t)P.ref_len;
+    const int64_t ref_words = (L + 15) / 16;
     for (uint32_t j0 = 0; j0 < m; j0 += 64) {
         const uint32_t j = j0 + (uint32_t)lane;
         const bool valid = j < m;
         uint32_t qb = 0;
         if (valid)
             qb = s ? 3u - base_of(P.reads, off + (m - 1 - j)) : base_of(P.reads, off + j);
-        const uint64_t x0 = (uint64_t)p + j;
-        const uint32_t r0 = valid && x0 < L ? base_of(P.ref, x0) : 4u;
-        const uint32_t rp = valid && x0 + 1 < L ? base_of(P.ref, x0 + 1) : 4u;
-        const uint32_t rm = valid && j >= 1 && x0 - 1 < L ? base_of(P.ref, x0 - 1) : 4u;
-        const uint64_t m0 = __ballot(valid && qb != r0);
-        const uint64_t mp = __ballot(valid && j >= 1 && qb != rp);
-        const uint64_t mm = __ballot(valid && j >= 2 && qb != rm);
-        cnt0 += __popcll(m0);
-        if (f0 == (int)m && m0)
-            f0 = (int)j0 + __ffsll((long long)m0) - 1;
-        if (mp)
-            lp = (int)j0 + 63 - __clzll((long long)mp);
-        if (mm)
-            lm = (int)j0 + 63 - __clzll((long long)mm);
+        const int64_t x = d + (int64_t)j - 2;           // reference position of diagonal d - 2
+        const int64_t w0 = x >= 0 ? x >> 4 : -1;
+        const uint32_t lo = valid && w0 >= 0 && w0 < ref_words ? P.ref[w0] : 0u;
+        const uint32_t hi = valid && w0 + 1 >= 0 && w0 + 1 < ref_words ? P.ref[w0 + 1] : 0u;
+        const uint64_t v = ((uint64_t)hi << 32) | lo;
+#pragma unroll
+        for (int o = 0; o < 5; ++o) {
+            const int64_t xo = x + o;
+            uint32_t rb = 4u;
+            if (valid && xo >= 0 && xo < L) {
+                if (w0 >= 0)
+                    rb = (uint32_t)(v >> (2 * (xo - 16 * w0))) & 3u;
+                else   // x < 0: xo lies in word 0, held in `hi`
+                    rb = (hi >> (2 * xo)) & 3u;
+            }
+            const uint64_t mk = __ballot(valid && qb != rb);
+            S.cnt[o] += __popcll(mk);
+            if (S.first[o] == (int)m && mk)
+                S.first[o] = (int)j0 + __ffsll((long long)mk) - 1;
+            if (mk)
+                S.last[o] = (int)j0 + 63 - __clzll((long long)mk);
+        }
     }
+    return S;
+}
+
+// The verdict at start p = d + t (t in -1..1) from the diagonals' statistics.
+__device__ Verdict verdict_at(const DiagStats &S, int t, uint32_t m, int64_t p, uint64_t L)
+{
+    const int c = t + 2;
+    const int cnt0 = S.cnt[c], f0 = S.first[c];
+    const int lp = S.last[c + 1] >= 1 ? S.last[c + 1] : -1;   // diagonal p + 1, j >= 1
+    const int lm = S.last[c - 1] >= 2 ? S.last[c - 1] : -1;   // diagonal p - 1, j >= 2
     const uint64_t pu = (uint64_t)p;
     if (pu + m <= L) {
         if (cnt0 == 0)
@@ -499,6 +533,9 @@ __global__ void __launch_bounds__(64 * kBWaves) k_stage_b(const StageBParams P)
                 last_s = s;
                 last_p = INT64_MIN;
             }
+            if (d + 1 <= last_p || d + 1 < 0)
+                continue;   // every start of this diagonal is taken or before the reference
+            const DiagStats S = scan_diagonals(P, off, m, s, d, lane);
             for (int t = -1; t <= 1; ++t) {
                 const int64_t p = d + t;
                 if (p <= last_p)
@@ -506,7 +543,7 @@ __global__ void __launch_bounds__(64 * kBWaves) k_stage_b(const StageBParams P)
                 last_p = p;
                 if (p < 0)
                     continue;
-                const Verdict v = verify_start(P, off, m, s, p, lane);
+                const Verdict v = verdict_at(S, t, m, p, P.ref_len);
                 if (v.e > 1)
                     continue;
                 if (v.e < best) {
