@@ -342,7 +342,7 @@ sw_status sw_seed_regions(sw_ctx *ctx, const sw_batch *reads, const void *d_inde
  * sw_stage_b's d_n_maps so that the reads stage B mapped skip stages C-E, as
  * in the paper). */
 #define SW_SEEKER_MAX_CALS 16
-#define SW_SEEKER_MAX_REGIONS 2048
+#define SW_SEEKER_MAX_REGIONS 1024
 sw_status sw_cal_seeker(sw_ctx *ctx, const sw_region *d_regions, const uint64_t *d_read_end,
                         uint32_t n_reads, uint64_t cap, uint32_t k, uint32_t merge_gap,
                         uint32_t min_len, const uint32_t *d_skip, sw_cal *d_cals, void *stream);

@@ -46,7 +46,7 @@ STEP = 12
 OFFSET = 7
 MAX_OCC = 64
 MAX_CALS = 16
-MAX_REGIONS = 2048
+MAX_REGIONS = 1024
 
 
 def seed_starts(m: int, k: int = K, step: int = STEP, offset: int = OFFSET) -> list[int]:

@@ -43,7 +43,7 @@ import numpy as np
 from . import seeker_ref as sr
 
 MAX_RECORDS = 16
-MAX_REGIONS = 2048
+MAX_REGIONS = sr.MAX_REGIONS
 EXACT, SUBST, DEL, INS = 0, 1, 2, 3
 
 

@@ -38,7 +38,7 @@ JUNCTION_DTYPE = np.dtype([("start", "<u8"), ("end", "<u8"), ("count", "<u4"),
 REGION_DTYPE = np.dtype([("first", "<u4"), ("read_pos", "<u2"), ("strand", "u1"),
                          ("reserved", "u1")])
 SW_SEEKER_MAX_CALS = 16
-SW_SEEKER_MAX_REGIONS = 2048
+SW_SEEKER_MAX_REGIONS = 1024
 SW_BMAP_MAX = 16
 BMAP_DTYPE = np.dtype([("first", "<u4"), ("last", "<u4"), ("strand", "u1"), ("edits", "u1"),
                        ("op", "u1"), ("reserved", "u1"), ("edit_pos", "<i4")])

@@ -305,7 +305,7 @@ __device__ void sort_keys(uint64_t *keys, uint32_t P2, int lane)
 // LDS by (strand, first) (bitonic sort), then the first lane merges them and
 // writes the read's kCals CAL slots (unused slots invalid).
 // ---------------------------------------------------------------------------
-constexpr int kSeekWaves = 2;
+constexpr int kSeekWaves = 4;
 
 __global__ void __launch_bounds__(64 * kSeekWaves) k_cal_seek(const sw_region *reg,
                                                               const uint64_t *read_end,
@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(64 * kSeekWaves) k_cal_seek(const sw_region *r
 // reference on the candidate's diagonal and its two neighbours, ballots give
 // the mismatch positions), and the records of the fewest edits are kept.
 // ---------------------------------------------------------------------------
-constexpr int kBWaves = 2;
+constexpr int kBWaves = 4;
 constexpr int kBMax = SW_BMAP_MAX;
 
 struct StageBParams {
