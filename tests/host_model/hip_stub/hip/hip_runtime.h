@@ -50,6 +50,7 @@ int model_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bo
 int __shfl(int v, int src, int width = 64);
 int __shfl_xor(int v, int mask, int width = 64);
 uint64_t __shfl_xor(uint64_t v, int mask, int width = 64);
+int __shfl_up(int v, unsigned delta, int width = 64);
 uint32_t atomicAdd(uint32_t *p, uint32_t v);
 uint32_t atomicSub(uint32_t *p, uint32_t v);
 unsigned long long atomicCAS(unsigned long long *p, unsigned long long cmp, unsigned long long v);

@@ -3,155 +3,22 @@
 // Compiles the unmodified kernel source (paper_1304_0681_amd/csrc/score.hip)
 // as C++ for the CPU, against the stand-in HIP header in hip_stub/, and runs
 // any instantiation of the packed int16 kernel or the int32 kernel on a
-// caller's batch.  Every input array lies against an inaccessible guard page
-// (after its end, or before its start), so an access outside an array stops
-// the process.
-//
-// Lanes are threads.  The 64 lanes of a wave meet at a barrier around every
-// cross-lane operation (each lane publishes its value, the barrier completes,
-// each lane reads its source lane, a second barrier completes): the lockstep
-// the hardware gives.  The instructions are emulated from their definitions:
-//   DPP row_shr:1 (0x111) / wave_shr:1 (0x138), all rows and banks, bound_ctrl
-//     off: lane l takes lane l - 1 (within its 16-lane row for row_shr), and a
-//     lane without a source keeps `old`;
-//   v_perm_b32: each result byte selects from the 8 bytes {hi, lo} (lo holds
-//     bytes 0-3): 0-7 a byte, 8-11 the sign of byte 1, 3, 5 or 7 spread over
-//     the byte, 12 the byte 0x00, 13-255 the byte 0xFF;
-//   v_alignbit_b32: ({hi, lo} >> (shift & 31)) low 32 bits;
-//   v_bfe_i32: the sign-extended `width` bits of src from bit `offset` (0 when
-//     the width is 0).
+// caller's batch, on the lockstep wave model of wave_model.h (lanes as
+// threads, cross-lane operations and the AMDGPU builtins emulated from their
+// definitions, every input array against an inaccessible guard page after its
+// end or before its start, so an access outside an array stops the process).
 #include <stdint.h>
 #include <string.h>
-#include <sys/mman.h>
-#include <unistd.h>
-
-#include <atomic>
-#include <cstdlib>
-#include <thread>
-#include <vector>
 
 #include "../../paper_1304_0681_amd/csrc/score.hip"
 
 thread_local ModelIdx threadIdx, blockIdx;
 
-namespace {
-
-// Sense-reversing barrier of the 64 lanes of a wave; spins, yielding the CPU,
-// since the lanes outnumber the host's cores.
-struct LaneBarrier {
-    std::atomic<int> count{64};
-    std::atomic<int> sense{0};
-    void arrive_and_wait()
-    {
-        const int s = sense.load(std::memory_order_relaxed);
-        if (count.fetch_sub(1, std::memory_order_acq_rel) == 1) {
-            count.store(64, std::memory_order_relaxed);
-            sense.store(s ^ 1, std::memory_order_release);
-        } else {
-            while (sense.load(std::memory_order_acquire) == s)
-                std::this_thread::yield();
-        }
-    }
-};
-
-struct Wave {
-    LaneBarrier bar;
-    uint64_t ex[64];
-};
-
-thread_local Wave *t_wave;
-
-int lane_id() { return (int)(threadIdx.x & 63u); }
-
-uint64_t exchange(uint64_t x, int src, bool has_src, uint64_t old)
-{
-    Wave &w = *t_wave;
-    w.ex[lane_id()] = x;
-    w.bar.arrive_and_wait();
-    const uint64_t r = has_src ? w.ex[src & 63] : old;
-    w.bar.arrive_and_wait();
-    return r;
-}
-
-uint8_t perm_byte(uint64_t d, uint32_t sel)
-{
-    sel &= 0xFF;
-    if (sel >= 13) return 0xFF;
-    if (sel == 12) return 0x00;
-    if (sel >= 8) return ((d >> (8 * (2 * (sel - 8) + 1) + 7)) & 1) ? 0xFF : 0x00;
-    return (uint8_t)(d >> (8 * sel));
-}
-
-}  // namespace
-
-int model_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl)
-{
-    if (row_mask != 0xF || bank_mask != 0xF || bound_ctrl)
-        abort();
-    const int l = lane_id();
-    if (ctrl == 0x111)
-        return (int)exchange((uint32_t)src, l - 1, (l & 15) != 0, (uint32_t)old);
-    if (ctrl == 0x138)
-        return (int)exchange((uint32_t)src, l - 1, l != 0, (uint32_t)old);
-    abort();
-}
-
-int __shfl(int v, int src, int) { return (int)exchange((uint32_t)v, src, true, 0); }
-int __shfl_xor(int v, int mask, int) { return (int)exchange((uint32_t)v, lane_id() ^ mask, true, 0); }
-uint64_t __shfl_xor(uint64_t v, int mask, int) { return exchange(v, lane_id() ^ mask, true, 0); }
-uint32_t atomicAdd(uint32_t *p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
-
-uint32_t model_perm(uint32_t hi, uint32_t lo, uint32_t sel)
-{
-    const uint64_t d = ((uint64_t)hi << 32) | lo;
-    uint32_t r = 0;
-    for (int k = 0; k < 4; ++k)
-        r |= (uint32_t)perm_byte(d, sel >> (8 * k)) << (8 * k);
-    return r;
-}
-
-uint32_t model_alignbit(uint32_t hi, uint32_t lo, uint32_t shift)
-{
-    return (uint32_t)((((uint64_t)hi << 32) | lo) >> (shift & 31));
-}
-
-int model_sbfe(int src, int offset, int width)
-{
-    offset &= 31;
-    width &= 31;
-    if (width == 0)
-        return 0;
-    const uint32_t u = (uint32_t)src >> offset;
-    const uint32_t m = width == 32 ? 0xFFFFFFFFu : ((1u << width) - 1u);
-    const uint32_t v = u & m;
-    const uint32_t sign = 1u << (width - 1);
-    return (int)((v ^ sign) - sign);
-}
+#include "wave_model.h"
 
 namespace {
 
-// A copy of `bytes` bytes against a guard page: after its end (at_end) or
-// before its start.
-struct Guarded {
-    char *base = nullptr;
-    size_t len = 0;
-    void *data = nullptr;
-    Guarded(const void *src, size_t bytes, bool at_end)
-    {
-        const size_t pg = (size_t)sysconf(_SC_PAGESIZE);
-        const size_t body = (bytes + pg - 1) / pg * pg + pg;
-        len = body + 2 * pg;
-        base = static_cast<char *>(mmap(nullptr, len, PROT_READ | PROT_WRITE,
-                                        MAP_PRIVATE | MAP_ANONYMOUS, -1, 0));
-        mprotect(base, pg, PROT_NONE);
-        mprotect(base + pg + body, pg, PROT_NONE);
-        char *p = at_end ? base + pg + body - bytes : base + pg;
-        if (bytes)
-            memcpy(p, src, bytes);
-        data = p;
-    }
-    ~Guarded() { munmap(base, len); }
-};
+using wave_model::Guarded;
 
 using KernelFn = void (*)(hpgsw::ScoreParams);
 
@@ -230,18 +97,7 @@ int model_score(int packed16, int G, int RPL, int mode, int strip, int waves, in
     P.strip_buf = strip ? static_cast<int2 *>(g_strip.data) : nullptr;
     P.strip_stride = strip_stride;
     // one block: waves 0..waves-1 of block 0 (wave index = threadIdx.x >> 6)
-    std::vector<Wave> wv(waves);
-    std::vector<std::thread> th;
-    for (int w = 0; w < waves; ++w)
-        for (int l = 0; l < 64; ++l)
-            th.emplace_back([&, w, l]() {
-                threadIdx = ModelIdx{(unsigned)(64 * w + l), 0, 0};
-                blockIdx = ModelIdx{0, 0, 0};
-                t_wave = &wv[w];
-                fn(P);
-            });
-    for (auto &t : th)
-        t.join();
+    wave_model::run_waves(waves, [&] { fn(P); });
     memcpy(hits_out, g_hits.data, sizeof(sw_hit) * n_pairs);
     return 0;
 }
