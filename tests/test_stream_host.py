@@ -55,3 +55,19 @@ def test_interrupted_loop_resumes_exactly_once(tmp_path):
     assert sorted(got) == [0, 1, 2, 3]
     run(None)
     assert got == {i: i * i for i in range(n)}
+
+
+def test_write_bed_sorted_with_strands(tmp_path):
+    """Junctions come out as BED lines sorted by position, with their counts as
+    scores and + / - for the GT-AG / CT-AC motif."""
+    import numpy as np
+
+    from paper_1304_0681_amd import JUNCTION_DTYPE
+    from paper_1304_0681_amd.splice import write_bed
+    j = np.array([(500, 900, 3, 1), (100, 250, 7, 0), (100, 180, 1, 0)], JUNCTION_DTYPE)
+    p = tmp_path / "j.bed"
+    write_bed(str(p), j, chrom="chr1")
+    rows = [ln.split("\t") for ln in p.read_text().splitlines()]
+    assert [(r[0], int(r[1]), int(r[2]), int(r[4]), r[5]) for r in rows] == \
+        [("chr1", 100, 180, 1, "+"), ("chr1", 100, 250, 7, "+"), ("chr1", 500, 900, 3, "-")]
+    assert len({r[3] for r in rows}) == 3
