@@ -102,18 +102,31 @@ __global__ void __launch_bounds__(1024) k_tile_offsets(uint32_t nt, T *tsum)
     }
 }
 
+// LDS word of tile entry i: one pad word per 32 keeps a thread's 16
+// consecutive entries off a single bank
+__device__ __forceinline__ int padded(int i) { return i + (i >> 5); }
+
 template <class T>
 __global__ void __launch_bounds__(256) k_tile_scan(const uint32_t *in, uint64_t n, const T *toff,
                                                    T *out)
 {
     __shared__ T part[256];
+    __shared__ T buf[kTile + kTile / 32];
     constexpr int PER = kTile / 256;   // consecutive entries per thread
-    const uint64_t my = (uint64_t)blockIdx.x * kTile + (uint64_t)threadIdx.x * PER;
-    uint32_t v[PER];
+    const uint64_t base = (uint64_t)blockIdx.x * kTile;
+    // coalesced loads through LDS, then each thread takes 16 consecutive entries
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = k * 256 + threadIdx.x;
+        buf[padded(i)] = base + i < n ? (T)in[base + i] : (T)0;
+    }
+    __syncthreads();
+    const int my = threadIdx.x * PER;
+    T v[PER];
     T s = 0;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        v[k] = my + k < n ? in[my + k] : 0u;
+        v[k] = buf[padded(my + k)];
         s += v[k];
     }
     part[threadIdx.x] = s;
@@ -128,8 +141,14 @@ __global__ void __launch_bounds__(256) k_tile_scan(const uint32_t *in, uint64_t 
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         run += v[k];
-        if (my + k < n)
-            out[my + k] = run;
+        buf[padded(my + k)] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = k * 256 + threadIdx.x;
+        if (base + i < n)
+            out[base + i] = buf[padded(i)];
     }
 }
 
