@@ -1043,7 +1043,7 @@ def main():
     ap.add_argument("--no-seeker", action="store_true", help="skip the device candidate seeker")
     ap.add_argument("--seeker-reads", type=int, default=1_000_000)
     ap.add_argument("--no-junctions", action="store_true", help="skip the splice-junction pass")
-    ap.add_argument("--junction-reads", type=int, default=50_000)
+    ap.add_argument("--junction-reads", type=int, default=200_000)
     ap.add_argument("--junction-steps", type=int, default=3)
     ap.add_argument("--junction-tb-mb", type=int, default=65536,
                     help="traceback scratch (MiB) of the whole-read alignments")

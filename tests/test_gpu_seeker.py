@@ -186,3 +186,39 @@ def test_stage_b_exact_and_skip(ctx):
             want = sr.cals(r, sr.regions(reads[r], oidx, 15, 12, 7, 40), 50, 20)
             assert [(int(c["read_id"]), int(c["first"]), int(c["last"]), int(c["strand"]), 1)
                     for c in row if c["valid"]] == want
+
+
+def test_config2_reads_fifty_thousand(ctx):
+    """50,000 reads of the benchmark workload (4 Mb GC-40 % reference, 1 %
+    substitutions, 0.1 % indels, 5 % random reads) through the k = 15 index:
+    every read's regions, CALs and stage B records equal the oracle's."""
+    from oracle import stageb_ref as sb
+    b = synth.config2(n_reads=50_000)
+    db = sw.DeviceBatch(ctx, b.ref, b.reads, b.read_off, b.read_len, np.zeros(0, sw.WINDOW_DTYPE))
+    idx = KmerIndex(ctx, db.ref2b, db.ref_len, k=15)
+    cs = CandidateSeeker(ctx, db, idx, stage_b=True)
+    cs.run()
+    torch.cuda.synchronize()
+    regs, end = cs.region_list()
+    recs, n_maps = cs.stage_b_maps()
+    cals = cs.cals.cpu().numpy().view(jr_dtype())
+    ref = jr.codes_of(b.ref.tobytes())
+    oidx = sr.build_index_fast(ref, 15)
+    reads = [jr.codes_of(b.read(r)) for r in range(b.n_reads)]
+    bgn = 0
+    for r, q in enumerate(reads):
+        want = sr.regions(q, oidx)
+        e = int(end[r])
+        got = [(int(x["strand"]), int(x["first"]), int(x["first"]) + 14, int(x["read_pos"]))
+               for x in regs[bgn:e]]
+        assert got == want, r
+        bgn = e
+        wb = sb.map_read(q, ref, oidx)
+        n = int(n_maps[r])
+        assert [(int(x["strand"]), int(x["first"]), int(x["last"]), int(x["edits"]),
+                 int(x["op"]), int(x["edit_pos"])) for x in recs[r, :n]] == wb, r
+        row = cals[r * sw.SW_SEEKER_MAX_CALS:(r + 1) * sw.SW_SEEKER_MAX_CALS]
+        wc = [] if n else sr.cals(r, want, 50, 20)
+        assert [(int(c["read_id"]), int(c["first"]), int(c["last"]), int(c["strand"]), 1)
+                for c in row if c["valid"]] == wc, r
+    assert 0.55 < (n_maps > 0).mean() < 0.75
