@@ -53,3 +53,28 @@ def test_cigar_string_formatting():
     buf = ctypes.create_string_buffer(4)
     a = (ctypes.c_uint32 * 1)((123 << 4) | 0)
     assert sw.lib().sw_cigar_string(a, 1, buf, 4) == -1
+
+
+def test_new_stage_calls_reject_bad_arguments():
+    """The seeker, stage B, CAL and junction calls refuse a missing context
+    before touching a device, and the index size is checked on the host."""
+    L = sw.lib()
+    assert L.sw_seed_cals(None, None, None, None, None, 0, 0, None, None) == sw.SW_E_INVALID
+    assert L.sw_join_cals(None, None, 0, 0, 0, 0, 0, None, None, None) == sw.SW_E_INVALID
+    assert L.sw_junctions_clear(None, None, None, 8, None) == sw.SW_E_INVALID
+    assert L.sw_detect_junctions(None, None, None, 0, None, None, 0, 0, 40, None, None, 8, None,
+                                 None, None) == sw.SW_E_INVALID
+    assert L.sw_list_junctions(None, None, None, 8, None, 0, None, None) == sw.SW_E_INVALID
+    assert L.sw_kmer_index_build(None, None, 0, 15, None, 0, None) == sw.SW_E_INVALID
+    assert L.sw_seed_regions(None, None, None, None, None, 0, None, None) == sw.SW_E_INVALID
+    assert L.sw_cal_seeker(None, None, None, 0, 0, 15, 0, 0, None, None, None) == sw.SW_E_INVALID
+    assert L.sw_stage_b(None, None, None, None, 0, None, None, None) == sw.SW_E_INVALID
+    # index sizes: 4 (4^k + 1) bytes of offsets, rounded to 256, plus 4 per k-mer
+    assert sw.sw_kmer_index_bytes(1000, 4) == ((4 * 257 + 255) // 256) * 256 + 4 * 997
+    assert sw.sw_kmer_index_bytes(4_000_000, 15) == 4 * (4 ** 15 + 1) + 252 + 4 * (4_000_000 - 14)
+    assert sw.sw_kmer_index_bytes(3, 4) == 1280          # no k-mer at all
+    for k in (3, 16):
+        with pytest.raises(sw.SwError):
+            sw.sw_kmer_index_bytes(1000, k)
+    with pytest.raises(sw.SwError):
+        sw.sw_kmer_index_bytes(1 << 33, 15)
