@@ -8,8 +8,9 @@
 //   bit 1  the deletion value of the NEXT column extends rather than opens
 //          (E(i,c) + gap_extend > H(i,c) + gap_open; an open wins ties)
 //   bit 0  the insertion value of the NEXT row extends rather than opens
-// Each bit is the sign of a difference, shifted into the lane's code word with
-// one funnel shift, so a cell costs no compare/select pairs.  The stop
+// Each bit is the sign of a difference; three bit selects gather a cell's four
+// and one funnel shift moves them into the lane's code word, so a cell costs
+// no compare/select pairs.  The stop
 // condition (H == 0) needs no bit: every step of the walk fixes the value of
 // the cell it moves to (a diagonal step subtracts s(i,c), a gap step the
 // extension or opening penalty), so the walk knows H along the path and stops
@@ -80,10 +81,27 @@ __device__ __forceinline__ int tb_wave_max(int v)
     return v;
 }
 
-// (w << 1) | sign bit of x
-__device__ __forceinline__ uint32_t ins_sign(uint32_t w, int x)
+// (w << 4) | the sign bits of a, b, c and d, a's the highest.  Every argument
+// lies in (-2^27, 2^27) (scores and penalties are at most 127 in magnitude and
+// H stays below 2^24), so its bits 31..28 all equal its sign bit: three bit
+// selects (v_bitop3_b32, table 0xE4: the third operand's set bits take the
+// first operand, its clear bits the second) gather bit 31 of a, 30 of b, 29 of
+// c and 28 of d, and one funnel shift moves the four in.  The selects issue at
+// the rate of an add, twice that of the funnel shift they replace three of.
+__device__ __forceinline__ uint32_t ins_signs4(uint32_t w, int a, int b, int c, int d)
 {
-    return __builtin_amdgcn_alignbit(w, (uint32_t)x, 31u);
+    const uint32_t ab = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, 0x80000000u, 0xE4);
+    const uint32_t cd = __builtin_amdgcn_bitop3_b32((uint32_t)c, (uint32_t)d, 0x20000000u, 0xE4);
+    const uint32_t y = __builtin_amdgcn_bitop3_b32(ab, cd, 0xC0000000u, 0xE4);
+    return __builtin_amdgcn_alignbit(w, y, 28u);
+}
+
+// Keeps x in a register at this point: the code bits of a cell are computed
+// right after its values instead of being sunk into the column's store branch,
+// which would keep every row's differences live until the column ends.
+__device__ __forceinline__ void keep_here(uint32_t &x)
+{
+    asm volatile("" : "+v"(x));
 }
 
 __device__ __forceinline__ uint32_t tb_window_word(const TBParams &P, int64_t rb, int64_t c0)
@@ -105,10 +123,14 @@ __device__ __forceinline__ uint32_t tb_window_word(const TBParams &P, int64_t rb
 
 // STRIP: queries longer than one strip of G*RPL rows (G == 64); the boundary
 // row between strips goes through the tail of the pair's slot.
-// The 20-row tile (150-nt queries) is held to 168 VGPRs for a third wave per SIMD,
-// which hides more of the walk; the other tiles already fit or would spill.
+// Waves per SIMD: the 13- and 20-row tiles (100- and 150-nt queries) are held to
+// 168 VGPRs for three, the 32-row tiles to 256 for two; the 8-row tiles fit
+// four as they are.
+template <int RPL>
+constexpr int tb_min_waves() { return RPL == 32 ? 2 : (RPL == 13 || RPL == 20) ? 3 : 1; }
+
 template <int G, int RPL, bool STRIP>
-__global__ void __launch_bounds__(64 * kWaves, RPL == 20 ? 3 : 1) k_sw_traceback(const TBParams P)
+__global__ void __launch_bounds__(64 * kWaves, tb_min_waves<RPL>()) k_sw_traceback(const TBParams P)
 {
     constexpr int PPW = 64 / G;
     constexpr int SR = G * RPL;
@@ -254,10 +276,8 @@ __global__ void __launch_bounds__(64 * kWaves, RPL == 20 ? 3 : 1) k_sw_traceback
                         // a clamped insertion value (0) is never the source of a
                         // positive H, so its bit ignores the clamp
                         uint32_t &cq = cw[r >> 3];
-                        cq = ins_sign(cq, dd - h);
-                        cq = ins_sign(cq, e - h);
-                        cq = ins_sign(cq, hg - ege);
-                        cq = ins_sign(cq, hg - gge);
+                        cq = ins_signs4(cq, dd - h, e - h, hg - ege, hg - gge);
+                        keep_here(cq);
                         E[r] = en;
                         g = gn;
                         cmax = max(cmax, h);
