@@ -57,6 +57,11 @@ struct TBParams {
     TbBand band;               // score-pass hits for the DP band (hits may be null)
 };
 
+template <bool B>
+struct Flag {
+    static constexpr bool value = B;
+};
+
 template <int G>
 __device__ __forceinline__ int tb_shift_up(int x, bool first, int boundary)
 {
@@ -195,8 +200,28 @@ __global__ void __launch_bounds__(64 * kWaves, tb_min_waves<RPL>()) k_sw_traceba
         uint32_t *runs = slot_codes + code_words + (STRIP ? 2 * (uint64_t)n_wave : 0);
         const int64_t rb = (int64_t)w.ref_begin + c_lo;   // window column 0 of the DP
 
+        // The end cell, when the caller's hit gives it (scored with ends): the DP
+        // then only has to store codes.  A wave tracks the best cell unless every
+        // pair of it has a known end.
         int best = 0, cbest = 0x7FFFFFFF, rbest = 0x7FFFFFFF;
+        bool known = false;
+        int kbest = 0, kcol = 0, krow = 0;
+        if (active && P.band.hits) {
+            const sw_hit hh = P.band.hits[pair];
+            if (hh.score == 0) {
+                known = true;
+            } else if (hh.score > 0 && hh.read_end >= 0 && hh.read_end < m && hh.ref_end >= c_lo &&
+                       hh.ref_end - c_lo < n) {
+                known = true;
+                kbest = hh.score;
+                kcol = hh.ref_end - c_lo;
+                krow = hh.read_end;
+            }
+        }
+        const bool track = __ballot(active && !known) != 0;
 
+        auto dp = [&](auto track_tag) {
+        constexpr bool TRACK = decltype(track_tag)::value;
         for (int strip = 0; strip < n_strips; ++strip) {
             const int row0 = strip * SR + l * RPL;
             int prof[RPL];
@@ -280,10 +305,11 @@ __global__ void __launch_bounds__(64 * kWaves, tb_min_waves<RPL>()) k_sw_traceba
                         keep_here(cq);
                         E[r] = en;
                         g = gn;
-                        cmax = max(cmax, h);
+                        if constexpr (TRACK)
+                            cmax = max(cmax, h);
                     }
                     gout = g;
-                    if (valid && cmax > lbest) {
+                    if (TRACK && valid && cmax > lbest) {
                         int row = RPL;
 #pragma unroll
                         for (int r = RPL - 1; r >= 0; --r)
@@ -303,7 +329,7 @@ __global__ void __launch_bounds__(64 * kWaves, tb_min_waves<RPL>()) k_sw_traceba
                 }
                 cur = nxt;
             }
-            {
+            if constexpr (TRACK) {
                 const bool better = lbest > best ||
                                     (lbest == best && lbest > 0 &&
                                      (lcol < cbest || (lcol == cbest && lrow < rbest)));
@@ -314,6 +340,11 @@ __global__ void __launch_bounds__(64 * kWaves, tb_min_waves<RPL>()) k_sw_traceba
                 }
             }
         }
+        };
+        if (track)
+            dp(Flag<true>{});
+        else
+            dp(Flag<false>{});
 #pragma unroll
         for (int off = 1; off < G; off <<= 1) {
             const int ob = __shfl_xor(best, off);
@@ -323,6 +354,11 @@ __global__ void __launch_bounds__(64 * kWaves, tb_min_waves<RPL>()) k_sw_traceba
             best = take ? ob : best;
             cbest = take ? oc : cbest;
             rbest = take ? orow : rbest;
+        }
+        if (known) {   // the same cell a tracking DP finds for a hit of this batch
+            best = kbest;
+            cbest = kcol;
+            rbest = krow;
         }
         __threadfence_block();   // code stores of the whole wave before the walk
 
