@@ -16,10 +16,12 @@
 // extension or opening penalty), so the walk knows H along the path and stops
 // where it reaches 0, which is the canonical rule (stop first, then diagonal,
 // deletion, insertion).
-// Column c stores its rows lane by lane: a lane's RPL rows fill ceil(RPL/8)
-// 32-bit words (8 codes each, the lane's first row in the highest nibble used),
-// so each lane writes whole words per step and a tile needs no multiple of 8
-// rows per lane (104 rows cover 100-nt queries, 160 rows 150-nt ones).  The
+// Codes are stored by step: at step t lane l computes column t - l, and its
+// RPL rows fill ceil(RPL/8) 32-bit words (8 codes each, the lane's first row in
+// the highest nibble used) at word (t * G + l) * ceil(RPL/8) of the slot, so the
+// lanes of a group store one contiguous run per step and a tile needs no
+// multiple of 8 rows per lane (104 rows cover 100-nt queries, 160 rows 150-nt
+// ones).  The
 // lanes of each group then walk back together from the end cell (smallest window
 // column, then smallest read row among the maxima), G cells per step, and the
 // first lane run-length encodes the ops.  Given the score pass's hits (score
@@ -155,7 +157,8 @@ __global__ void __launch_bounds__(64 * kWaves, tb_min_waves<RPL>()) k_sw_traceba
     // even one wave every pair of the class is marked and skipped.
     const uint64_t nmax = P.maxlen[P.cls], mmax = P.maxlen[kNumClasses + P.cls];
     const uint64_t strips_max = STRIP ? (mmax + SR - 1) / SR : 1;
-    const uint64_t slot_words = strips_max * G * WPL * nmax + (STRIP ? 2 * nmax : 0) + mmax + nmax + 8;
+    const uint64_t slot_words =
+        strips_max * G * WPL * (nmax + G - 1) + (STRIP ? 2 * nmax : 0) + mmax + nmax + 8;
     const uint64_t fit = P.codes_words / ((uint64_t)PPW * slot_words);
     // (a slot is addressed with 32-bit word offsets)
     const bool no_room = fit == 0 || slot_words > 0xFFFFFFFFull;
@@ -194,8 +197,8 @@ __global__ void __launch_bounds__(64 * kWaves, tb_min_waves<RPL>()) k_sw_traceba
         const int T = n_wave + G - 1;
         const int m_wave = STRIP ? tb_wave_max(m) : SR;
         const int n_strips = STRIP ? (m_wave + SR - 1) / SR : 1;
-        const uint32_t col_words = (uint32_t)(n_strips * G * WPL);   // code words per column
-        const uint64_t code_words = (uint64_t)col_words * (uint64_t)n_wave;
+        const uint32_t col_words = (uint32_t)(n_strips * G * WPL);   // code words per step
+        const uint64_t code_words = (uint64_t)col_words * (uint64_t)T;
         int2 *bnd = reinterpret_cast<int2 *>(slot_codes + code_words);  // strip boundary row
         uint32_t *runs = slot_codes + code_words + (STRIP ? 2 * (uint64_t)n_wave : 0);
         const int64_t rb = (int64_t)w.ref_begin + c_lo;   // window column 0 of the DP
@@ -319,7 +322,9 @@ __global__ void __launch_bounds__(64 * kWaves, tb_min_waves<RPL>()) k_sw_traceba
                         lrow = row0 + row;
                     }
                     if (valid) {
-                        uint32_t *dst = slot_codes + (uint64_t)c * col_words + (uint32_t)((strip * G + l) * WPL);
+                        // codes are stored by step, so a group's lanes write one
+                        // contiguous run
+                        uint32_t *dst = slot_codes + (uint64_t)t * col_words + (uint32_t)((strip * G + l) * WPL);
 #pragma unroll
                         for (int q = 0; q < WPL; ++q)
                             dst[q] = cw[q];
@@ -383,7 +388,7 @@ __global__ void __launch_bounds__(64 * kWaves, tb_min_waves<RPL>()) k_sw_traceba
                 const int sp = STRIP ? (int)((uint32_t)ii / (uint32_t)SR) : 0;
                 const int rs = ii - sp * SR;
                 const int ln = (int)((uint32_t)rs / (uint32_t)RPL), r = rs - ln * RPL;
-                const uint32_t wv = slot_codes[(uint32_t)cc * col_words + (uint32_t)((sp * G + ln) * WPL + (r >> 3))];
+                const uint32_t wv = slot_codes[(uint32_t)(cc + ln) * col_words + (uint32_t)((sp * G + ln) * WPL + (r >> 3))];
                 const int nq = min(8, RPL - (r & ~7));   // rows in the row's word
                 return (wv >> (4u * (uint32_t)(nq - 1 - (r & 7)))) & 15u;
             };
