@@ -65,13 +65,15 @@ T_MAP = 200
 #   int32, per cell: score select (4), diagonal add (2), H + go (2), E and F
 #     (add 2 + max 4 each), H max3 and the zero floor (4 + 4), running max (4):
 #     32 cycles per 64 cells -> 4,915 GCUPS
-#   traceback (int32 with 4 code bits per cell), per cell: the int32 recurrence
-#     (26 cycles with the running max as max3 over two rows), four differences
-#     (2 each) and four bit inserts (4 each): 50 cycles per 64 cells -> 3,146 GCUPS
+#   traceback (int32 with 4 code bits per cell), per cell, with the end cell
+#     given by the score pass (no running max): the int32 recurrence without
+#     the running max (24 cycles), four differences (2 each), three bit selects
+#     (v_bitop3_b32, 2 each) and one funnel shift (4): 42 cycles per 64 cells
+#     -> 3,745 GCUPS
 SIMD_CYCLES = 1024 * 2.4e9
 PEAK_GCUPS_INT16X2 = SIMD_CYCLES * 128 / 42 / 1e9
 PEAK_GCUPS_INT32 = SIMD_CYCLES * 64 / 32 / 1e9
-PEAK_GCUPS_TRACEBACK = SIMD_CYCLES * 64 / 50 / 1e9
+PEAK_GCUPS_TRACEBACK = SIMD_CYCLES * 64 / 42 / 1e9
 PATHS = {1: "int32", 2: "int32+ends", 3: "int16x2"}
 # HBM bytes per launch of the dominant kernel on the default workload, from two
 # rocprofv3 PMC runs (FETCH_SIZE, then WRITE_SIZE) of this script with
