@@ -18,6 +18,10 @@ device buffers and no host round trip:
              become N ops and are counted in a device hash table that
              accumulates over batches (sw_detect_junctions, task iv)
 
+SeekerSplicedPass finds the seeds' candidate windows on the device first
+(regions, CALs and joining of the seeds: stages C and D), so that nothing but
+the reads and the reference enters the pass.
+
 The junction table is read out with junctions() (sorted) and written as BED
 with write_bed().
 """
@@ -45,7 +49,7 @@ class SplicedPass:
                  seed_scoring=SEED_SCORING, long_scoring=LONG_SCORING, min_seed_score: int = 100,
                  ext: int = 30, max_gap: int = 5000, min_score: int = 100, min_intron: int = 40,
                  table_capacity: int = 1 << 20, ops_stride: int = 256,
-                 tb_scratch_mb: int | None = 16384):
+                 tb_scratch_mb: int | None = 16384, seed_ops_stride: int | None = None):
         import torch
         self.ctx, self.seed_db, self.long_db = ctx, seed_db, long_db
         self.long_scoring = long_scoring
@@ -58,7 +62,9 @@ class SplicedPass:
         dev = "cuda"
         n_seeds, n_long = seed_db.n_reads, long_db.n_reads
         self.n_seeds, self.n_long = n_seeds, n_long
-        self.seeds = AlignPass(ctx, seed_db, seed_scoring, band=True)
+        # (a seed's CAL reads its alignment's span only, so truncated seed CIGARs
+        # change nothing downstream)
+        self.seeds = AlignPass(ctx, seed_db, seed_scoring, band=True, ops_stride=seed_ops_stride)
         sr = np.ascontiguousarray(seed_read, dtype=np.uint32)
         assert len(sr) == n_seeds
         self.seed_read = torch.from_numpy(sr.view(np.int32)).to(dev)
@@ -132,6 +138,35 @@ class SplicedPass:
         return (self.best_pair.cpu().numpy().view(np.uint32), self.best_score.cpu().numpy(),
                 aln_to_numpy(self.aln), self.ops.cpu().numpy().view(np.uint32),
                 self.n_junc.cpu().numpy().view(np.uint32))
+
+
+class SeekerSplicedPass(SplicedPass):
+    """SplicedPass with the seeds' candidate windows found on the device: the
+    seeds' regions, CALs and joined windows (CandidateSeeker: stages C and D,
+    then stage E tasks i and ii on the seeds) run ahead of the seed alignment,
+    so the reads and the reference are the whole input.
+
+    `seed_db`: the seeds (its own windows are not used); `index`: the k-mer
+    index of the reference (KmerIndex); max_occ, merge_gap and min_len are the
+    seeker's, seed_ext and seed_max_gap the joining of a seed's CALs (a seed
+    that crosses an intron has a CAL on each side).  The remaining arguments
+    are SplicedPass's."""
+
+    def __init__(self, ctx, seed_db: DeviceBatch, index, seed_read, long_db: DeviceBatch,
+                 max_occ: int = 64, merge_gap: int = 50, min_len: int = 20, seed_ext: int = 30,
+                 seed_max_gap: int = 5000, seed_ops_stride: int = 64, **kw):
+        from .seeker import CandidateSeeker
+        self.seeker = CandidateSeeker(ctx, seed_db, index, max_occ=max_occ, merge_gap=merge_gap,
+                                      min_len=min_len, ext=seed_ext, max_gap=seed_max_gap)
+        super().__init__(ctx, self.seeker.view, seed_read, long_db,
+                         seed_ops_stride=seed_ops_stride, **kw)
+
+    def run_seeker(self, stream=None):
+        self.seeker.run(stream)
+
+    def run(self, stream=None):
+        self.run_seeker(stream)
+        super().run(stream)
 
 
 def write_bed(path: str, junctions: np.ndarray, chrom: str = "ref") -> None:

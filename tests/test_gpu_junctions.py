@@ -197,7 +197,7 @@ def spliced_long():
     return long_b, seed_b, truth
 
 
-def _oracle_chain(long_b, seed_b, truth, p):
+def _oracle_chain(long_b, seed_b, truth, p, every_seed_has_windows=True):
     """The spliced pass computed by the oracle alone."""
     ns = seed_b.n_reads
     res, _ = oracle.align_batch(seed_b, SEED_SCORING, mode=0)
@@ -208,8 +208,14 @@ def _oracle_chain(long_b, seed_b, truth, p):
     idx = np.nonzero(res["score"] == best[rid])[0][::-1]
     bp[rid[idx]] = idx
     bp = bp.astype(np.uint32)
-    assert (bp != 0xFFFFFFFF).all()          # every seed has windows
-    sa, _ = oracle.align_batch(seed_b, SEED_SCORING, mode=1, sel=bp)
+    if every_seed_has_windows:
+        assert (bp != 0xFFFFFFFF).all()
+    sa = np.zeros(ns, oracle.RESULT_DTYPE)
+    sa["score"] = -1
+    sa["ref_begin"] = sa["ref_end"] = -1
+    with_win = bp != 0xFFFFFFFF
+    if with_win.any():
+        sa[with_win] = oracle.align_batch(seed_b, SEED_SCORING, mode=1, sel=bp[with_win])[0]
     cals = jr.seed_cals(seed_b.windows, bp, sa, truth["seed_read"], p["min_seed_score"])
     joined = jr.join_cals(cals, long_b.n_reads, len(long_b.ref), ext=p["ext"],
                           max_gap=p["max_gap"])
@@ -291,3 +297,63 @@ def test_spliced_pass_vs_oracle(ctx, spliced_long):
     found = set(got) & truth_j
     assert len(found) >= 0.8 * len(truth_j), (len(found), len(truth_j))
     assert len(set(got) - truth_j) <= 0.05 * len(got)
+
+
+def test_spliced_pass_from_seeker_vs_oracle(ctx, spliced_long):
+    """The same spliced reads with the seeds' windows found on the device (k = 15
+    index, regions, CALs and joining of the seeds) instead of the generator's:
+    the seeds' windows equal the oracle seeker's, and every later step equals
+    the oracle's chain run on those windows."""
+    from oracle import seeker_ref as sr
+    from paper_1304_0681_amd.seeker import KmerIndex
+    from paper_1304_0681_amd.splice import SeekerSplicedPass
+    long_b, seed_b, truth = spliced_long
+    p = dict(min_seed_score=100, ext=30, max_gap=5000, min_score=100, min_intron=MIN_INTRON,
+             ops_stride=256)
+    ref = jr.codes_of(long_b.ref.tobytes())
+    oidx = sr.build_index_fast(ref, 15)
+    ns = seed_b.n_reads
+    ocals = []
+    for s in range(ns):
+        c = sr.cals(s, sr.regions(jr.codes_of(seed_b.read(s)), oidx, 15, 12, 7, 64), 50, 20)
+        ocals += c + [(s, 0, 0, 0, 0)] * (sw.SW_SEEKER_MAX_CALS - len(c))
+    jw = jr.join_cals(ocals, ns, len(ref), ext=30, max_gap=5000)
+    swin = np.array([(r, b, n, st, 0) for r, b, n, st in jw], dtype=synth.WINDOW_DTYPE)
+    seed_w = synth.Batch(ref=seed_b.ref, reads=seed_b.reads, read_off=seed_b.read_off,
+                         read_len=seed_b.read_len, windows=swin, truth={})
+    want = _oracle_chain(long_b, seed_w, truth, p, every_seed_has_windows=False)
+
+    seed_db = sw.DeviceBatch(ctx, seed_b.ref, seed_b.reads, seed_b.read_off, seed_b.read_len,
+                             np.zeros(0, sw.WINDOW_DTYPE))
+    idx = KmerIndex(ctx, seed_db.ref2b, seed_db.ref_len, k=15)
+    long_db = sw.DeviceBatch(ctx, None, long_b.reads, long_b.read_off, long_b.read_len,
+                             np.zeros(0, sw.WINDOW_DTYPE), ref2b=(seed_db.ref2b, seed_db.ref_len))
+    sp = SeekerSplicedPass(ctx, seed_db, idx, truth["seed_read"], long_db, max_occ=64,
+                           merge_gap=50, min_len=20, seed_ext=30, seed_max_gap=5000,
+                           min_seed_score=100, ext=30, max_gap=5000, min_score=100,
+                           min_intron=MIN_INTRON, table_capacity=1 << 16, ops_stride=256,
+                           tb_scratch_mb=4096)
+    sp.run()
+    torch.cuda.synchronize()
+    gw = sp.seeker.windows()
+    assert [(int(x["read_id"]), int(x["ref_begin"]), int(x["len"]), int(x["strand"]))
+            for x in gw] == jw
+    assert len(jw) >= 0.9 * ns
+    assert (sp.seeds.best_pair.cpu().numpy().view(np.uint32) == want["bp"]).all()
+    assert _cal_tuples(sp.cals.cpu().numpy().view(CAL_DTYPE)) == want["cals"]
+    w = sp.windows()
+    assert [(int(x["read_id"]), int(x["ref_begin"]), int(x["len"]), int(x["strand"]))
+            for x in w] == want["joined"]
+    bp, bs, aln, ops, nj = sp.results()
+    assert (bp == want["lbp"]).all() and (bs == want["lbest"]).all()
+    has = want["lbp"] != 0xFFFFFFFF
+    for f in ("score", "read_begin", "read_end", "ref_begin", "ref_end", "n_ops", "status"):
+        assert (aln[f][has] == want["la"][f][has]).all(), f
+    for r in np.nonzero(has)[0]:
+        n = int(aln["n_ops"][r])
+        assert (ops[r, :n] == want["lops"][r, :n]).all(), r
+    got = {(int(j["start"]), int(j["end"]), int(j["strand"])): int(j["count"])
+           for j in sp.junctions()}
+    assert got == want["table"]
+    truth_j = {(int(a), int(b), int(s)) for a, b, s in truth["junctions"]}
+    assert len(set(got) & truth_j) >= 0.8 * len(truth_j), (len(set(got) & truth_j), len(truth_j))
