@@ -603,7 +603,8 @@ def bench_junctions(args):
 
     import paper_1304_0681_amd as sw
     import synth
-    from paper_1304_0681_amd.splice import SplicedPass
+    from paper_1304_0681_amd.seeker import KmerIndex
+    from paper_1304_0681_amd.splice import SeekerSplicedPass, SplicedPass
 
     t0 = time.perf_counter()
     long_b, seed_b, truth = synth.spliced_long(n_reads=args.junction_reads)
@@ -618,36 +619,52 @@ def bench_junctions(args):
         # of its class, and this budget keeps four waves per SIMD in flight
         sp = SplicedPass(ctx, seed_db, truth["seed_read"], long_db, table_capacity=1 << 21,
                          tb_scratch_mb=args.junction_tb_mb)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-        phase = np.zeros(5)
-        wall = []
-        for rep in range(1 + args.junction_steps):
-            sp.clear()
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            ev[0].record()
-            sp.run_seeds()
-            ev[1].record()
-            sp.run_cals()
-            ev[2].record()
-            sw.sw_batch_score(ctx, sp.long_view, sp.long_scoring, 0, sp.hits)
-            sw.sw_best_per_read(ctx, sp.long_view, sp.hits, sp.min_score, sp.best_pair,
-                                sp.best_score, None)
-            ev[3].record()
-            sw.sw_batch_traceback(ctx, sp.long_view, sp.long_scoring, sp.best_pair, sp.n_long,
-                                  sp.aln, sp.ops, sp.ops_stride)
-            ev[4].record()
-            sp.run_junctions()
-            ev[5].record()
-            torch.cuda.synchronize()
-            if rep >= 1:
-                wall.append(time.perf_counter() - t1)
-                phase += [ev[i].elapsed_time(ev[i + 1]) for i in range(5)]
-        phase /= args.junction_steps
-        t_step = float(np.mean(wall))
+        truth_j = {(int(a), int(b), int(s)) for a, b, s in truth["junctions"]}
+
+        def timed_pass(sp, seeker: bool):
+            """Per-phase event times (ms, averaged over the timed steps) and the
+            wall time per step of one spliced pass."""
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+            phase = np.zeros(6)
+            wall = []
+            for rep in range(1 + args.junction_steps):
+                sp.clear()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                ev[0].record()
+                if seeker:
+                    sp.run_seeker()
+                ev[1].record()
+                sp.run_seeds()
+                ev[2].record()
+                sp.run_cals()
+                ev[3].record()
+                sw.sw_batch_score(ctx, sp.long_view, sp.long_scoring, 0, sp.hits)
+                sw.sw_best_per_read(ctx, sp.long_view, sp.hits, sp.min_score, sp.best_pair,
+                                    sp.best_score, None)
+                ev[4].record()
+                sw.sw_batch_traceback(ctx, sp.long_view, sp.long_scoring, sp.best_pair,
+                                      sp.n_long, sp.aln, sp.ops, sp.ops_stride)
+                ev[5].record()
+                sp.run_junctions()
+                ev[6].record()
+                torch.cuda.synchronize()
+                if rep >= 1:
+                    wall.append(time.perf_counter() - t1)
+                    phase += [ev[i].elapsed_time(ev[i + 1]) for i in range(6)]
+            return phase / args.junction_steps, float(np.mean(wall))
+
+        def found(sp):
+            j = sp.junctions()
+            got = {(int(r["start"]), int(r["end"]), int(r["strand"])) for r in j}
+            tp = len(got & truth_j)
+            return j, got, tp
+
+        phase6, t_step = timed_pass(sp, seeker=False)
+        phase = phase6[1:]
         w = sp.windows()
         bp, bs, aln, ops, nj = sp.results()
-        j = sp.junctions()
+        j, got, tp = found(sp)
         dropped = int(sp.dropped.item())
         m = long_b.read_len[w["read_id"]].astype(np.int64)
         n = np.minimum(w["len"].astype(np.int64),
@@ -655,9 +672,39 @@ def bench_junctions(args):
         long_cells = int((m * n).sum())
         ok = bp < len(w)
         tb_cells = int((m[bp[ok]] * n[bp[ok]]).sum())
-        truth_j = {(int(a), int(b), int(s)) for a, b, s in truth["junctions"]}
-        got = {(int(r["start"]), int(r["end"]), int(r["strand"])) for r in j}
-        tp = len(got & truth_j)
+        reads_aligned = int((bs >= sp.min_score).sum())
+        del sp
+        # the same reads with the seeds' windows found on the device (k = 15 index,
+        # regions, CALs and joining of the seeds) instead of the generator's
+        t2 = time.perf_counter()
+        idx = KmerIndex(ctx, seed_db.ref2b, seed_db.ref_len, k=15)
+        torch.cuda.synchronize()
+        t_idx = time.perf_counter() - t2
+        seeds_only = sw.DeviceBatch(ctx, None, seed_b.reads, seed_b.read_off, seed_b.read_len,
+                                    np.zeros(0, sw.WINDOW_DTYPE),
+                                    ref2b=(seed_db.ref2b, seed_db.ref_len))
+        sk = SeekerSplicedPass(ctx, seeds_only, idx, truth["seed_read"], long_db,
+                               table_capacity=1 << 21, tb_scratch_mb=args.junction_tb_mb)
+        kph, k_step = timed_pass(sk, seeker=True)
+        sw_win = sk.seeker.windows()
+        _, k_got, k_tp = found(sk)
+        k_bp, k_bs, _, _, _ = sk.results()
+        from_seeker = {
+            "note": "seeds' candidate windows from the device seeker (k = 15 index built once, "
+                    "regions, CALs, joining within 5,000 nt) instead of the generator's",
+            "index_build_ms": round(t_idx * 1e3, 2),
+            "ms_per_step": round(k_step * 1e3, 3),
+            "reads_per_s": round(long_b.n_reads / k_step, 1),
+            "seed_windows": int(len(sw_win)),
+            "seed_window_len_mean": round(float(sw_win["len"].mean()), 1) if len(sw_win) else 0.0,
+            "phase_ms": {"seeker": round(kph[0], 3), "seeds_score_best_traceback": round(kph[1], 3),
+                         "cals_and_join": round(kph[2], 3), "long_score_and_best": round(kph[3], 3),
+                         "long_traceback": round(kph[4], 3), "junction_detect": round(kph[5], 4)},
+            "reads_aligned": int((k_bs >= sk.min_score).sum()),
+            "junctions_found": len(k_got), "true_positives": k_tp,
+            "sensitivity": round(k_tp / max(len(truth_j), 1), 4),
+            "precision": round(k_tp / max(len(k_got), 1), 4),
+        }
         # alignments that report a junction: the run's bytes (ops read and
         # written, record, window, pair id) are the detection's whole traffic
         det_bytes = int(4 * 2 * aln["n_ops"][ok].astype(np.int64).sum()) + 44 * int(ok.sum())
@@ -681,7 +728,7 @@ def bench_junctions(args):
             "long_traceback_cells": tb_cells,
             "long_traceback_gcups": round(tb_cells / (phase[3] / 1e3) / 1e9, 1),
             "junction_detect_gb_per_s": round(det_bytes / (phase[4] / 1e3) / 1e9, 1),
-            "reads_aligned": int((bs >= sp.min_score).sum()),
+            "reads_aligned": reads_aligned,
             "truth_junctions": len(truth_j), "junctions_found": len(got), "true_positives": tp,
             "sensitivity": round(tp / max(len(truth_j), 1), 4),
             "precision": round(tp / max(len(got), 1), 4),
@@ -689,6 +736,7 @@ def bench_junctions(args):
             "table_dropped": dropped,
             "traceback_scratch_mb": args.junction_tb_mb,
             "generation_seconds": round(t_gen, 1),
+            "from_seeker": from_seeker,
         }
     finally:
         sw.sw_ctx_destroy(ctx)
