@@ -542,11 +542,12 @@ sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *b, const sw_scoring *s
     ctx->tb = static_cast<uint32_t *>(buf);
     ctx->tb_bytes = have;
     const TbBand band{d_hits, sc->match, -sc->gap_open, -sc->gap_extend};
-    HIP_TRY(ctx, launch_bucket(*b, d_pair_ids, n_sel, bs, nullptr, d_aln, s, default_edges(), band));
+    const ClassEdges tb_edges = traceback_edges();
+    HIP_TRY(ctx, launch_bucket(*b, d_pair_ids, n_sel, bs, nullptr, d_aln, s, tb_edges, band));
     const int wpb = traceback_waves_per_block();
     const int grid = std::max(1, ctx->n_cu * 16 / wpb);
     for (int c = 0; c < kNumClasses; ++c) {
-        if (c > 0 && (uint64_t)kDefaultClasses[c - 1].m_max >= b->reads_len)
+        if (c > 0 && (uint64_t)tb_edges.m_max[c - 1] >= b->reads_len)
             continue;   // no read of this batch can fall in this class
         HIP_TRY(ctx, launch_traceback_class(c, *b, *sc, d_pair_ids, bs.ids, bs.seg, bs.counter,
                                             d_aln, d_ops, ops_stride, ctx->tb,

@@ -120,6 +120,8 @@ hipError_t launch_best(const sw_batch &b, const sw_hit *hits, uint64_t *keys, in
 hipError_t launch_select_windows(const sw_batch &b, const uint32_t *ids, uint32_t n, sw_window *out,
                                  hipStream_t st);
 int traceback_waves_per_block();
+// Query-length class bounds of the traceback (its own above 512 bases).
+ClassEdges traceback_edges();
 hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &sc,
                                   const uint32_t *sel, const uint32_t *ids, const uint32_t *seg,
                                   uint32_t *counter, sw_aln *aln, uint32_t *ops,

@@ -359,9 +359,10 @@ def test_config2_full_size_sampled(ctx):
 
 
 def test_traceback_scratch_too_small_marks_pairs(ctx):
-    """With a 1 MiB traceback budget the 1,025-2,048-base query class (64 lanes x
-    32 rows, whose code slot for a 1,100-base window is about 1.1 MiB) has no
-    room: its pairs get status bit 2 and score -1 and are not aligned, while
+    """With a 1 MiB traceback budget the traceback class of queries above 1,024
+    bases (strips of 64 lanes x 32 rows, whose code slot for a 1,100-base window
+    is about 1.2 MiB) has no room: its pairs get status bit 2 and score -1 and
+    are not aligned, while
     the 100-base pairs of the same call align exactly; with the default budget
     every pair aligns."""
     b = edge_batch(51, [100, 1500], [300, 1100], div=0.03)
