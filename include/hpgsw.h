@@ -317,8 +317,13 @@ typedef struct {
     uint8_t reserved;   /* written as 0 */
 } sw_region;
 
-/* Regions of every read of `reads` (its reads only: the windows and reference
- * are not used) against the index d_index (built with sp->k).  Read r's
+/* Regions of every read of `reads` (its reads, and its reference length for
+ * the index size check: the windows and reference bases are not used) against
+ * the index d_index of index_bytes bytes, built by sw_kmer_index_build with
+ * sp->k from the batch's reference.  An index_bytes below
+ * sw_kmer_index_bytes(reads->ref_len, sp->k) is refused (SW_E_RANGE), so a k
+ * larger than the index's cannot read past it; an index of another reference
+ * or a smaller k gives undefined regions (never out-of-bounds accesses).  Read r's
  * regions are d_regions[read_end[r - 1] .. read_end[r]) (read_end[-1] = 0;
  * d_read_end: device uint64 array of n_reads), in seed order (first phase
  * first), strand 0 before strand 1 for each seed, reference positions
@@ -326,8 +331,8 @@ typedef struct {
  * Reads outside the packed reads get none.  Context scratch: about 4 bytes per
  * read. */
 sw_status sw_seed_regions(sw_ctx *ctx, const sw_batch *reads, const void *d_index,
-                          const sw_seed_params *sp, sw_region *d_regions, uint64_t cap,
-                          uint64_t *d_read_end, void *stream);
+                          uint64_t index_bytes, const sw_seed_params *sp, sw_region *d_regions,
+                          uint64_t cap, uint64_t *d_read_end, void *stream);
 
 /* CALs of every read from its regions (the first SW_SEEKER_MAX_REGIONS of
  * them that lie below cap): per strand, regions sorted by first base merge

@@ -137,7 +137,7 @@ def lib() -> ctypes.CDLL:
         L.sw_list_junctions.argtypes = [P, P, P, U32, P, U32, P, P]
         L.sw_kmer_index_bytes.argtypes = [U64, U32, ctypes.POINTER(ctypes.c_uint64)]
         L.sw_kmer_index_build.argtypes = [P, P, U64, U32, P, U64, P]
-        L.sw_seed_regions.argtypes = [P, ctypes.POINTER(sw_batch), P,
+        L.sw_seed_regions.argtypes = [P, ctypes.POINTER(sw_batch), P, U64,
                                       ctypes.POINTER(sw_seed_params), P, U64, P, P]
         L.sw_cal_seeker.argtypes = [P, P, P, U32, U64, U32, U32, U32, P, P, P]
         L.sw_stage_b.argtypes = [P, ctypes.POINTER(sw_batch), P, P, U64, P, P, P]
@@ -392,12 +392,16 @@ def sw_kmer_index_build(ctx, d_ref2b, ref_len, k, d_index, index_bytes, stream=N
                                           int(index_bytes), _stream_ptr(stream)))
 
 
-def sw_seed_regions(ctx, batch, d_index, params, d_regions, cap, d_read_end, stream=None):
-    """`params`: (k, step, offset, max_occ) or sw_seed_params."""
+def sw_seed_regions(ctx, batch, d_index, params, d_regions, cap, d_read_end, stream=None,
+                    index_bytes=None):
+    """`params`: (k, step, offset, max_occ) or sw_seed_params; `index_bytes`
+    defaults to the size of the d_index tensor."""
     sp = params if isinstance(params, sw_seed_params) else sw_seed_params(*[int(x) for x in params])
-    _check(ctx, lib().sw_seed_regions(ctx, ctypes.byref(batch.c), _ptr(d_index), ctypes.byref(sp),
-                                      _ptr(d_regions), int(cap), _ptr(d_read_end),
-                                      _stream_ptr(stream)))
+    if index_bytes is None:
+        index_bytes = d_index.numel() * d_index.element_size()
+    _check(ctx, lib().sw_seed_regions(ctx, ctypes.byref(batch.c), _ptr(d_index), int(index_bytes),
+                                      ctypes.byref(sp), _ptr(d_regions), int(cap),
+                                      _ptr(d_read_end), _stream_ptr(stream)))
 
 
 def sw_cal_seeker(ctx, d_regions, d_read_end, n_reads, cap, k, merge_gap, min_len, d_cals,

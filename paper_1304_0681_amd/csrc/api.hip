@@ -1720,8 +1720,8 @@ sw_status sw_kmer_index_build(sw_ctx *ctx, const uint32_t *d_ref2b, uint64_t ref
 }
 
 sw_status sw_seed_regions(sw_ctx *ctx, const sw_batch *reads, const void *d_index,
-                          const sw_seed_params *sp, sw_region *d_regions, uint64_t cap,
-                          uint64_t *d_read_end, void *stream)
+                          uint64_t index_bytes, const sw_seed_params *sp, sw_region *d_regions,
+                          uint64_t cap, uint64_t *d_read_end, void *stream)
 {
     if (!ctx)
         return fail(nullptr, SW_E_INVALID, "ctx is NULL");
@@ -1730,6 +1730,12 @@ sw_status sw_seed_regions(sw_ctx *ctx, const sw_batch *reads, const void *d_inde
     sw_status st = check_seed_params(ctx, sp);
     if (st)
         return st;
+    uint64_t need = 0;
+    if ((st = sw_kmer_index_bytes(reads->ref_len, sp->k, &need)))
+        return fail(ctx, st, "%s", g_noctx_err.c_str());
+    if (index_bytes < need)
+        return fail(ctx, SW_E_RANGE, "index of %llu bytes, an index with k = %u of this reference "
+                    "takes %llu", (unsigned long long)index_bytes, sp->k, (unsigned long long)need);
     if (reads->n_reads == 0)
         return SW_OK;
     if (!reads->d_read_len || !reads->d_read_off || !reads->d_reads2b || !d_index || !d_read_end ||

@@ -66,7 +66,7 @@ def test_new_stage_calls_reject_bad_arguments():
                                  None, None) == sw.SW_E_INVALID
     assert L.sw_list_junctions(None, None, None, 8, None, 0, None, None) == sw.SW_E_INVALID
     assert L.sw_kmer_index_build(None, None, 0, 15, None, 0, None) == sw.SW_E_INVALID
-    assert L.sw_seed_regions(None, None, None, None, None, 0, None, None) == sw.SW_E_INVALID
+    assert L.sw_seed_regions(None, None, None, 0, None, None, 0, None, None) == sw.SW_E_INVALID
     assert L.sw_cal_seeker(None, None, None, 0, 0, 15, 0, 0, None, None, None) == sw.SW_E_INVALID
     assert L.sw_stage_b(None, None, None, None, 0, None, None, None) == sw.SW_E_INVALID
     # index sizes: 4 (4^k + 1) bytes of offsets, rounded to 256, plus 4 per k-mer

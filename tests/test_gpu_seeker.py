@@ -222,3 +222,24 @@ def test_config2_reads_fifty_thousand(ctx):
         assert [(int(c["read_id"]), int(c["first"]), int(c["last"]), int(c["strand"]), 1)
                 for c in row if c["valid"]] == wc, r
     assert 0.55 < (n_maps > 0).mean() < 0.75
+
+
+def test_seed_regions_refuses_an_index_too_small_for_k(ctx):
+    """An index built with k = 10 (or a size below what k = 15 needs) is refused
+    for seeds of 15 bases before any kernel runs."""
+    ref = reference_with_repeats(68, 200_000)
+    db = _db(ctx, ref, [ref[1000:1100]])
+    idx10 = KmerIndex(ctx, db.ref2b, db.ref_len, k=10)
+    regions = torch.empty(64 * 8, dtype=torch.uint8, device="cuda")
+    end = torch.empty(1, dtype=torch.int64, device="cuda")
+    with pytest.raises(sw.SwError) as e:
+        sw.sw_seed_regions(ctx, db, idx10.buf, (15, 12, 7, 64), regions, 64, end)
+    assert e.value.status == sw.SW_E_RANGE
+    idx15 = KmerIndex(ctx, db.ref2b, db.ref_len, k=15)
+    with pytest.raises(sw.SwError) as e:
+        sw.sw_seed_regions(ctx, db, idx15.buf, (15, 12, 7, 64), regions, 64, end,
+                           index_bytes=idx15.nbytes - 4)
+    assert e.value.status == sw.SW_E_RANGE
+    sw.sw_seed_regions(ctx, db, idx15.buf, (15, 12, 7, 64), regions, 64, end)
+    torch.cuda.synchronize()
+    assert int(end[0].item()) > 0
