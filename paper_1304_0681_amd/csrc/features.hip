@@ -228,7 +228,64 @@ __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, con
             bm_all[bm_wave + i] = 0;
         for (int x = lane; x < 256; x += 64)
             L.lut[x] = f2bf((float)x / Pdf);
+        // ---- the words of a group of windows as one stream: cwo[k] is the first
+        // stream word of window k of the group (cwo[Gn] the total), and cwr[k]
+        // holds cwo[k + 1] in a register for the window search of fetch()
+        uint32_t cwr[kG];
+        uint32_t total = 0, c = 0, gbase = 0;
+        auto prep = [&](uint32_t cgx) {
+            const int Gx = min((int)(K - cgx), kG);
+            uint32_t nw = 0;
+            if (lane < Gx) {
+                const int nf = L.wnf[cgx + lane];
+                const uint64_t rb = L.wrb[cgx + lane];
+                nw = nf > 0 ? (uint32_t)(((rb + (uint64_t)nf - 1) >> 4) - (rb >> 4) + 1) : 0u;
+                L.rj[lane] = 16.f / (float)max(nf - kK + 1, 1);
+            }
+#pragma unroll
+            for (int off = 1; off < kG; off <<= 1) {
+                const uint32_t t = __shfl_up(nw, off, kG);
+                if ((lane & (kG - 1)) >= off)
+                    nw += t;
+            }
+            if (lane < kG)
+                L.cwo[lane + 1] = nw;
+            if (lane == 0)
+                L.cwo[0] = 0;
+            // lanes at or beyond Gx hold the total, so windows past the group
+            // never pass the search's test
+#pragma unroll
+            for (int k = 0; k < kG; ++k)
+                cwr[k] = (uint32_t)__builtin_amdgcn_readlane((int)nw, k);
+            total = cwr[kG - 1];
+            gbase = cgx;
+            c = 0;
+        };
+        // the window of stream word wn (< total) and its two reference words;
+        // c (the window of the lane's latest fetched word) only moves forward
+        auto fetch = [&](uint32_t wn, uint32_t &cw, uint32_t &x0, uint32_t &x1) {
+            uint32_t cn = 0;
+#pragma unroll
+            for (int k = 0; k < kG - 1; ++k)
+                cn += cwr[k] <= wn ? 1u : 0u;
+            c = cn;
+            cw = c;
+            const uint64_t gw = (uint64_t)(L.wrb[gbase + c] >> 4) + (uint64_t)(wn - L.cwo[c]);
+            x0 = b.d_ref2b[min(gw, ref_words - 1)];
+            x1 = b.d_ref2b[min(gw + 1, ref_words - 1)];
+        };
+        uint32_t pca = 0, pa0 = 0, pa1 = 0, pcb = 0, pb0 = 0, pb1 = 0;
+        // the first chunk of a group is fetched ahead, here for the first group
+        // (its loads overlap the query tables' construction)
+        auto first_fetch = [&]() {
+            if ((uint32_t)lane < total)
+                fetch(lane, pca, pa0, pa1);
+            if ((uint32_t)lane + 64 < total)
+                fetch(lane + 64, pcb, pb0, pb1);
+        };
+        prep(0);
         lds_fence();
+        first_fetch();
         // ---- query k-mer tables and prefilters (orientation 0: read, 1: reverse complement)
         uint32_t dupf = 0;   // bit o: a k-mer of orientation o occurs twice in the query
         for (int e = lane; e < 2 * P; e += 64) {
@@ -273,37 +330,8 @@ __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, con
         };
         for (uint32_t cg = 0; cg < K; cg += kG) {
             const int Gn = min((int)(K - cg), kG);
-            // ---- the group's words as one stream
-            uint32_t nw = 0;
-            if (lane < Gn) {
-                const int nf = L.wnf[cg + lane];
-                const uint64_t rb = L.wrb[cg + lane];
-                nw = nf > 0 ? (uint32_t)(((rb + (uint64_t)nf - 1) >> 4) - (rb >> 4) + 1) : 0u;
-                L.rj[lane] = 16.f / (float)max(nf - kK + 1, 1);
-            }
-#pragma unroll
-            for (int off = 1; off < kG; off <<= 1) {
-                const uint32_t t = __shfl_up(nw, off, kG);
-                if ((lane & (kG - 1)) >= off)
-                    nw += t;
-            }
-            if (lane < kG)
-                L.cwo[lane + 1] = nw;
-            if (lane == 0)
-                L.cwo[0] = 0;
-            lds_fence();
-            const uint32_t total = L.cwo[Gn];
-            // Each lane owns two stream words per step (a 128-word chunk): c is the
-            // window of the lane's latest fetched word and only moves forward.
-            uint32_t c = 0;
-            auto fetch = [&](uint32_t wn, uint32_t &cw, uint32_t &x0, uint32_t &x1) {
-                while (c + 1 < (uint32_t)Gn && L.cwo[c + 1] <= wn)
-                    ++c;
-                cw = c;
-                const uint64_t gw = (uint64_t)(L.wrb[cg + c] >> 4) + (uint64_t)(wn - L.cwo[c]);
-                x0 = b.d_ref2b[min(gw, ref_words - 1)];
-                x1 = b.d_ref2b[min(gw + 1, ref_words - 1)];
-            };
+            // Each lane owns two stream words per step (a 128-word chunk); the
+            // first chunk was fetched ahead (prep and first_fetch).
             // bitmap candidates of one word: positions i whose k-mer may occur in the query
             auto scan = [&](uint32_t wc, uint32_t cc, uint32_t a0, uint32_t a1, uint32_t &cand,
                             uint32_t &head, int &j0) {
@@ -351,23 +379,19 @@ __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, con
                     ++o2;
                 }
             };
-            uint32_t pca = 0, pa0 = 0, pa1 = 0, pcb = 0, pb0 = 0, pb1 = 0;
-            if ((uint32_t)lane < total)
-                fetch(lane, pca, pa0, pa1);
-            if ((uint32_t)lane + 64 < total)
-                fetch(lane + 64, pcb, pb0, pb1);
-            for (uint32_t W = 0; W < total; W += 128) {
+            const uint32_t g_total = total;
+            for (uint32_t W = 0; W < g_total; W += 128) {
                 const uint32_t wa = W + lane, wb = W + 64 + lane;
                 const uint32_t ca = pca, a0 = pa0, a1 = pa1, cb = pcb, b0 = pb0, b1 = pb1;
-                if (wa + 128 < total)
+                if (wa + 128 < g_total)
                     fetch(wa + 128, pca, pa0, pa1);
-                if (wb + 128 < total)
+                if (wb + 128 < g_total)
                     fetch(wb + 128, pcb, pb0, pb1);
                 uint32_t candA = 0, headA = 0, candB = 0, headB = 0;
                 int j0A = 0, j0B = 0;
-                if (wa < total)
+                if (wa < g_total)
                     scan(wa, ca, a0, a1, candA, headA, j0A);
-                if (wb < total)
+                if (wb < g_total)
                     scan(wb, cb, b0, b1, candB, headB, j0B);
                 // offsets of every lane's candidates in the chunk's list (prefix over the wave)
                 const uint32_t cnt = __popc(candA) + __popc(candB);
@@ -419,6 +443,13 @@ __global__ void __launch_bounds__(64 * kWavesF) k_features(const sw_batch b, con
                 }
             }
             lds_fence();
+            // the next group's stream and first chunk, ahead of this group's
+            // statistics (which read neither cwo nor rj)
+            if (cg + kG < K) {
+                prep(cg + kG);
+                lds_fence();
+                first_fetch();
+            }
             // ---- statistics, eight lanes per window
             {
                 const int cw = lane >> 3, q = lane & 7;
