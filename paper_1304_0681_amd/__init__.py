@@ -23,6 +23,8 @@ SW_OPT_INT16 = 1
 SW_OPT_BLOCKS_PER_CU = 2
 SW_OPT_TB_SCRATCH_MB = 3
 SW_NOALLOC_MAX_PAIRS = 1 << 22
+# CIGAR op codes ((length << 4) | code)
+SW_OP_M, SW_OP_I, SW_OP_D, SW_OP_N, SW_OP_S = 0, 1, 2, 3, 4
 OP_NAMES = "MIDNS"
 
 HIT_DTYPE = np.dtype([("score", "<i4"), ("read_end", "<i4"), ("ref_end", "<i4")])
