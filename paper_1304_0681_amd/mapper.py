@@ -11,9 +11,10 @@ runs, with fixed device buffers and no host round trip:
              and its alignment with CIGAR (AlignPass with the band of the best
              hit)
 
-results() merges the two sources into one record per read: the stage B
-record (the first of its best stratum, with the CIGAR of its one edit) or the
-SW alignment of the best window, or unmapped.
+results() merges the two sources into one record per read (arrays, no
+per-read host loop): the stage B record (the first of its best stratum, with
+the CIGAR of its one edit) or the SW alignment of the best window, or
+unmapped.
 """
 from __future__ import annotations
 
@@ -31,15 +32,6 @@ UNMAPPED, STAGE_B, STAGE_E = 0, 1, 2
 RECORD_DTYPE = np.dtype([("source", "u1"), ("strand", "u1"), ("n_records", "u1"),
                          ("edits", "i1"), ("score", "<i4"), ("ref_begin", "<i8"),
                          ("ref_end", "<i8"), ("read_begin", "<i4"), ("read_end", "<i4")])
-
-
-def _stage_b_cigar(m: int, op: int, pos: int) -> list[int]:
-    """CIGAR ops ((len << 4) | code) of a stage B record of an m-base read."""
-    if op == 2:                       # deletion before query base pos
-        return [(pos << 4) | SW_OP_M, (1 << 4) | SW_OP_D, ((m - pos) << 4) | SW_OP_M]
-    if op == 3:                       # query base pos inserted
-        return [(pos << 4) | SW_OP_M, (1 << 4) | SW_OP_I, ((m - pos - 1) << 4) | SW_OP_M]
-    return [(m << 4) | SW_OP_M]       # exact or one substitution
 
 
 class ShortReadMapper:
@@ -62,37 +54,59 @@ class ShortReadMapper:
         self.align.run(stream, pack=False)
 
     def results(self):
-        """(records, cigars): one RECORD_DTYPE row per read, and each read's CIGAR
-        ops (a list per read; stage E CIGARs include soft clips)."""
+        """(records, ops, n_ops): one RECORD_DTYPE row per read, and its CIGAR ops
+        ((length << 4) | code, ops[r, :n_ops[r]]; stage E CIGARs include soft
+        clips and stop at ops_stride ops)."""
         n = self.db.n_reads
         maps, n_maps = self.seeker.stage_b_maps()
         bp, bs, aln, ops = self.align.results()
         win = self.seeker.windows()
         m = self.db.read_len.cpu().numpy().view(np.uint16).astype(np.int64)[:n]
         rec = np.zeros(n, RECORD_DTYPE)
-        rec["score"] = -1
-        rec["ref_begin"] = rec["ref_end"] = -1
-        rec["read_begin"] = rec["read_end"] = -1
-        rec["edits"] = -1
-        cigars: list[list[int]] = [[] for _ in range(n)]
-        for r in range(n):
-            k = int(n_maps[r])
-            if k:
-                x = maps[r, 0]
-                rec[r] = (STAGE_B, int(x["strand"]), k, int(x["edits"]), -1, int(x["first"]),
-                          int(x["last"]), 0, int(m[r]) - 1)
-                cigars[r] = _stage_b_cigar(int(m[r]), int(x["op"]), int(x["edit_pos"]))
-            elif (bp[r] != 0xFFFFFFFF and int(bs[r]) >= self.t_map
-                  and (int(aln["status"][r]) & ~1) == 0):
-                # (status bit 0: CIGAR cut at ops_stride; the coordinates stand)
-                w = win[bp[r]]
-                a = aln[r]
-                rec[r] = (STAGE_E, int(w["strand"]), 1, -1, int(a["score"]),
-                          int(w["ref_begin"]) + int(a["ref_begin"]),
-                          int(w["ref_begin"]) + int(a["ref_end"]), int(a["read_begin"]),
-                          int(a["read_end"]))
-                cigars[r] = [int(o) for o in ops[r, :int(a["n_ops"])]]
-        return rec, cigars
+        for f, v in (("score", -1), ("ref_begin", -1), ("ref_end", -1), ("read_begin", -1),
+                     ("read_end", -1), ("edits", -1)):
+            rec[f] = v
+        out = np.zeros((n, ops.shape[1]), np.uint32)
+        n_ops = np.zeros(n, np.int64)
+        # stage B: the first record of the best stratum, the CIGAR of its one edit
+        isb = n_maps > 0
+        x = maps[:, 0]
+        rec["source"][isb] = STAGE_B
+        rec["strand"][isb] = x["strand"][isb]
+        rec["n_records"][isb] = n_maps[isb]
+        rec["edits"][isb] = x["edits"][isb]
+        rec["ref_begin"][isb] = x["first"][isb]
+        rec["ref_end"][isb] = x["last"][isb]
+        rec["read_begin"][isb] = 0
+        rec["read_end"][isb] = m[isb] - 1
+        op, pos = x["op"].astype(np.int64), x["edit_pos"].astype(np.int64)
+        gap = isb & ((op == 2) | (op == 3))
+        code = np.where(op == 2, SW_OP_D, SW_OP_I)
+        tail = np.where(op == 2, m - pos, m - pos - 1)
+        plain = isb & ~gap
+        out[plain, 0] = (m[plain] << 4) | SW_OP_M
+        n_ops[plain] = 1
+        out[gap, 0] = (pos[gap] << 4) | SW_OP_M
+        out[gap, 1] = (1 << 4) | code[gap]
+        out[gap, 2] = (tail[gap] << 4) | SW_OP_M
+        n_ops[gap] = 3
+        # stage E: the best window's alignment (status bit 0: CIGAR cut at
+        # ops_stride; the coordinates stand)
+        ise = (~isb & (bp != 0xFFFFFFFF) & (bs >= self.t_map)
+               & ((aln["status"].astype(np.int64) & ~1) == 0))
+        w = win[bp[ise]]
+        a = aln[ise]
+        rec["source"][ise] = STAGE_E
+        rec["strand"][ise] = w["strand"]
+        rec["n_records"][ise] = 1
+        rec["score"][ise] = a["score"]
+        rec["ref_begin"][ise] = w["ref_begin"].astype(np.int64) + a["ref_begin"]
+        rec["ref_end"][ise] = w["ref_begin"].astype(np.int64) + a["ref_end"]
+        rec["read_begin"][ise] = a["read_begin"]
+        rec["read_end"][ise] = a["read_end"]
+        out[ise] = ops[ise]
+        n_ops[ise] = a["n_ops"]
+        return rec, out, n_ops
 
 
 def cigar_string(ops) -> str:
