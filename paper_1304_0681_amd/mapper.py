@@ -109,10 +109,40 @@ class ShortReadMapper:
         return rec, out, n_ops
 
 
+def write_sam(path: str, rec: np.ndarray, ops: np.ndarray, n_ops: np.ndarray, reads: np.ndarray,
+              read_off: np.ndarray, read_len: np.ndarray, ref_len: int, chrom: str = "ref",
+              names=None) -> None:
+    """Mapper records as SAM text (one line per read, in read order): flag 16 for
+    the reverse strand (SEQ then holds the reverse complement, as aligned), 4
+    for unmapped reads; POS is 1-based; AS:i carries the SW score, NM:i the
+    edits of a stage B record; MAPQ is 255 (not computed).  reads / read_off /
+    read_len: the batch's ASCII reads."""
+    comp = bytes.maketrans(b"ACGTacgtN", b"TGCAtgcaN")
+    with open(path, "w") as f:
+        f.write(f"@HD\tVN:1.6\tSO:unsorted\n@SQ\tSN:{chrom}\tLN:{int(ref_len)}\n"
+                f"@PG\tID:hpgsw\tPN:paper_1304_0681_amd\n")
+        for r in range(len(rec)):
+            x = rec[r]
+            o, m = int(read_off[r]), int(read_len[r])
+            seq = bytes(reads[o:o + m])
+            name = names[r] if names is not None else f"r{r}"
+            if int(x["source"]) == UNMAPPED:
+                f.write(f"{name}\t4\t*\t0\t0\t*\t*\t0\t0\t{seq.decode()}\t*\n")
+                continue
+            rev = int(x["strand"]) == 1
+            if rev:
+                seq = seq.translate(comp)[::-1]
+            tag = (f"AS:i:{int(x['score'])}" if int(x["source"]) == STAGE_E
+                   else f"NM:i:{int(x['edits'])}")
+            f.write(f"{name}\t{16 if rev else 0}\t{chrom}\t{int(x['ref_begin']) + 1}\t255\t"
+                    f"{cigar_string(ops[r, :int(n_ops[r])])}\t*\t0\t0\t{seq.decode()}\t*\t{tag}\n")
+
+
 def cigar_string(ops) -> str:
     """'12M1D88M'-style text of CIGAR ops."""
     letters = "MIDNS"
     return "".join(f"{int(o) >> 4}{letters[int(o) & 15]}" for o in ops)
 
 
-__all__ = ["ShortReadMapper", "RECORD_DTYPE", "UNMAPPED", "STAGE_B", "STAGE_E", "cigar_string"]
+__all__ = ["ShortReadMapper", "RECORD_DTYPE", "UNMAPPED", "STAGE_B", "STAGE_E", "cigar_string",
+           "write_sam"]
