@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(64 * kInferWaves) __attribute__((amdgpu_waves_
 k_mlp_infer(const MlpDev W, const uint16_t *__restrict__ X, uint32_t n, const uint32_t *d_n,
             float *__restrict__ logits)
 {
-    __shared__ uint16_t h1s[kInferWaves][16][kHidden + 8];   // +8: spread LDS banks
+    __shared__ __attribute__((aligned(16))) uint16_t h1s[kInferWaves][16][kHidden + 8];   // +8: spread LDS banks
     __shared__ float b1s[kHidden], b2s[kHidden], w3s[kHidden];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -124,19 +124,19 @@ k_mlp_infer(const MlpDev W, const uint16_t *__restrict__ X, uint32_t n, const ui
     if (tile < n_tiles)
         load_x(tile);
     for (; tile < n_tiles; tile += stride) {
-        // layer 1: D(sample lk*4 + r, unit nt*16 + li), bias as the accumulator's start
+        // layer 1, transposed: D(unit nt*16 + lk*4 + r, sample li) = W1 x^T (the
+        // weight fragments serve as the A operand unchanged: same lanes, same
+        // k), so each lane holds four consecutive units of one sample and
+        // writes them to the sample's LDS row in one 8-byte store
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) {
-            const float b1 = b1s[nt * 16 + li];
-            f32x4 acc = {b1, b1, b1, b1};
-            acc = mfma(xn[0], w1[nt][0], acc);
-            acc = mfma(xn[1], w1[nt][1], acc);
+            const int u0 = nt * 16 + lk * 4;
+            f32x4 acc = {b1s[u0], b1s[u0 + 1], b1s[u0 + 2], b1s[u0 + 3]};
+            acc = mfma(w1[nt][0], xn[0], acc);
+            acc = mfma(w1[nt][1], xn[1], acc);
             const uint32_t h01 = pk_bf16(fmaxf(acc[0], 0.f), fmaxf(acc[1], 0.f));
             const uint32_t h23 = pk_bf16(fmaxf(acc[2], 0.f), fmaxf(acc[3], 0.f));
-            h1s[wv][lk * 4 + 0][nt * 16 + li] = (uint16_t)h01;
-            h1s[wv][lk * 4 + 1][nt * 16 + li] = (uint16_t)(h01 >> 16);
-            h1s[wv][lk * 4 + 2][nt * 16 + li] = (uint16_t)h23;
-            h1s[wv][lk * 4 + 3][nt * 16 + li] = (uint16_t)(h23 >> 16);
+            *reinterpret_cast<uint2 *>(&h1s[wv][li][u0]) = make_uint2(h01, h23);
         }
         // the inputs are consumed: start loading the next tile's
         if (tile + stride < n_tiles)
