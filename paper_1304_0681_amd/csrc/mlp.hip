@@ -113,17 +113,14 @@ k_mlp_infer(const MlpDev W, const uint16_t *__restrict__ X, uint32_t n, const ui
     const uint32_t n_tiles = (n + 15) / 16;
     const uint32_t stride = gridDim.x * kInferWaves;
     uint32_t tile = blockIdx.x * kInferWaves + wv;
-    // the next tile's inputs are loaded while the current one is computed
-    bf16x8 xn[2];
-    auto load_x = [&](uint32_t t) {
+    // inputs are loaded two tiles ahead: two register sets take turns
+    auto load_x = [&](bf16x8 (&x)[2], uint32_t t) {
         const uint32_t row = t * 16 + li;
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk)
-            xn[kk] = row < n ? load8(X + (uint64_t)row * kIn + kk * 32 + lk * 8) : zero8();
+            x[kk] = row < n ? load8(X + (uint64_t)row * kIn + kk * 32 + lk * 8) : zero8();
     };
-    if (tile < n_tiles)
-        load_x(tile);
-    for (; tile < n_tiles; tile += stride) {
+    auto process = [&](bf16x8 (&xn)[2], uint32_t tile) {
         // layer 1, transposed: D(unit nt*16 + lk*4 + r, sample li) = W1 x^T (the
         // weight fragments serve as the A operand unchanged: same lanes, same
         // k), so each lane holds four consecutive units of one sample and
@@ -138,9 +135,9 @@ k_mlp_infer(const MlpDev W, const uint16_t *__restrict__ X, uint32_t n, const ui
             const uint32_t h23 = pk_bf16(fmaxf(acc[2], 0.f), fmaxf(acc[3], 0.f));
             *reinterpret_cast<uint2 *>(&h1s[wv][li][u0]) = make_uint2(h01, h23);
         }
-        // the inputs are consumed: start loading the next tile's
-        if (tile + stride < n_tiles)
-            load_x(tile + stride);
+        // the inputs are consumed: this register set takes the tile two ahead
+        if (tile + 2 * stride < n_tiles)
+            load_x(xn, tile + 2 * stride);
         __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): LDS writes done (same wave)
         __builtin_amdgcn_wave_barrier();
         bf16x8 ha[4];
@@ -175,6 +172,16 @@ k_mlp_infer(const MlpDev W, const uint16_t *__restrict__ X, uint32_t n, const ui
             }
         }
         __builtin_amdgcn_wave_barrier();   // LDS tile reused by the next tile
+    };
+    bf16x8 xa[2], xb[2];
+    if (tile < n_tiles)
+        load_x(xa, tile);
+    if (tile + stride < n_tiles)
+        load_x(xb, tile + stride);
+    for (; tile < n_tiles; tile += 2 * stride) {
+        process(xa, tile);
+        if (tile + stride < n_tiles)
+            process(xb, tile + stride);
     }
 }
 
