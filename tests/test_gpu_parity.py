@@ -136,6 +136,30 @@ def test_traceback_band_from_score_ends(ctx, sc):
     assert_aln_equal(a, o, ref, rops)
 
 
+def test_traceback_mixed_known_and_unknown_ends(ctx):
+    """Hits where a random half of the pairs has its end cell removed (score kept,
+    ends -1): the waves that mix pairs with and without a known end track the best
+    cell for all of them, pairs without an end use the whole window, and every
+    alignment still equals the oracle's."""
+    b = edge_batch(17, EDGE_M, EDGE_N)
+    ref, rops = oracle.align_batch(b, SC, mode=1)
+    db = sw.DeviceBatch.from_synth(ctx, b)
+    hits = torch.full((b.n_pairs, 3), -7, dtype=torch.int32, device="cuda")
+    sw.sw_batch_score(ctx, db, SC, sw.SW_WANT_ENDS, hits)
+    drop = torch.from_numpy(np.random.default_rng(18).random(b.n_pairs) < 0.5).cuda()
+    hits[drop, 1] = -1
+    hits[drop, 2] = -1
+    sel = np.arange(b.n_pairs, dtype=np.uint32)
+    stride = int(b.read_len.max()) + int(b.windows["len"].max()) + 4
+    ids = torch.from_numpy(sel.view(np.int32)).cuda()
+    aln = torch.full((len(sel), 7), -7, dtype=torch.int32, device="cuda")
+    ops = torch.zeros((len(sel), stride), dtype=torch.int32, device="cuda")
+    sw.sw_batch_traceback(ctx, db, SC, ids, len(sel), aln, ops, stride, hits=hits)
+    torch.cuda.synchronize()
+    assert_aln_equal(sw.aln_to_numpy(aln), ops.cpu().numpy().view(np.uint32), ref, rops)
+    assert int(drop.sum().item()) > 100
+
+
 def test_select_windows(ctx):
     """sw_select_windows copies the windows of the given pair ids; ids at or past
     the batch's pairs (also past a device-side pair count) give a window with an
