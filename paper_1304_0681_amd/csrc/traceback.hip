@@ -148,6 +148,9 @@ __global__ void __launch_bounds__(64 * kWaves, tb_min_waves<RPL>()) k_sw_traceba
     const bool first = l == 0;
     const uint32_t seg_begin = P.seg[2 * P.cls];
     const uint32_t seg_end = P.seg[2 * P.cls + 1];
+    // an empty class ends at once, before every wave takes a turn at the task counter
+    if (seg_end <= seg_begin)
+        return;
     const uint32_t n_tasks = (seg_end - seg_begin + PPW - 1) / PPW;
     const int go = P.go, ge = P.ge;
     const uint32_t wave_global = blockIdx.x * kWaves + (threadIdx.x >> 6);
