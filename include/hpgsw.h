@@ -198,8 +198,11 @@ sw_status sw_select_windows(sw_ctx *ctx, const sw_batch *batch, const uint32_t *
  * d_pair_ids).  With it, each pair's DP covers only the window columns an
  * alignment of that score ending at that cell can reach, which gives the same
  * alignments and CIGARs in less time; pairs whose hit has no end, and every
- * pair when a gap penalty is 0, use the whole window.  Hits that do not come
- * from that call give undefined alignments (never out-of-bounds accesses). */
+ * pair when a gap penalty is 0, use the whole window; the walk starts at the
+ * hit's end cell.  Hits that do not come from that call give undefined
+ * alignments (never out-of-bounds accesses).  Pairs are bucketed by query
+ * length as in sw_batch_score up to 512 bases, and above into 513-768,
+ * 769-1,024 and longer queries (the last in strips of 2,048 rows). */
 sw_status sw_batch_traceback(sw_ctx *ctx, const sw_batch *batch, const sw_scoring *sc,
                              const uint32_t *d_pair_ids, uint32_t n_sel, sw_aln *d_aln,
                              uint32_t *d_ops, uint32_t ops_stride, const sw_hit *d_hits,
