@@ -639,12 +639,9 @@ def bench_junctions(args):
                 ev[2].record()
                 sp.run_cals()
                 ev[3].record()
-                sw.sw_batch_score(ctx, sp.long_view, sp.long_scoring, 0, sp.hits)
-                sw.sw_best_per_read(ctx, sp.long_view, sp.hits, sp.min_score, sp.best_pair,
-                                    sp.best_score, None)
+                sp.run_long_best()
                 ev[4].record()
-                sw.sw_batch_traceback(ctx, sp.long_view, sp.long_scoring, sp.best_pair,
-                                      sp.n_long, sp.aln, sp.ops, sp.ops_stride)
+                sp.run_long_traceback()
                 ev[5].record()
                 sp.run_junctions()
                 ev[6].record()
@@ -669,7 +666,11 @@ def bench_junctions(args):
         m = long_b.read_len[w["read_id"]].astype(np.int64)
         n = np.minimum(w["len"].astype(np.int64),
                        len(long_b.ref) - w["ref_begin"].astype(np.int64))
-        long_cells = int((m * n).sum())
+        # the score pass covers the windows of reads with two or more
+        per_read = np.bincount(w["read_id"].astype(np.int64), minlength=long_b.n_reads)
+        multi = per_read[w["read_id"].astype(np.int64)] >= 2
+        long_cells = int((m * n)[multi].sum())
+        sole_reads = int((per_read == 1).sum())
         ok = bp < len(w)
         tb_cells = int((m[bp[ok]] * n[bp[ok]]).sum())
         reads_aligned = int((bs >= sp.min_score).sum())
@@ -698,7 +699,7 @@ def bench_junctions(args):
             "seed_windows": int(len(sw_win)),
             "seed_window_len_mean": round(float(sw_win["len"].mean()), 1) if len(sw_win) else 0.0,
             "phase_ms": {"seeker": round(kph[0], 3), "seeds_score_best_traceback": round(kph[1], 3),
-                         "cals_and_join": round(kph[2], 3), "long_score_and_best": round(kph[3], 3),
+                         "cals_and_join": round(kph[2], 3), "long_best_window": round(kph[3], 3),
                          "long_traceback": round(kph[4], 3), "junction_detect": round(kph[5], 4)},
             "reads_aligned": int((k_bs >= sk.min_score).sum()),
             "junctions_found": len(k_got), "true_positives": k_tp,
@@ -720,9 +721,14 @@ def bench_junctions(args):
             "reads_per_s": round(long_b.n_reads / t_step, 1),
             "phase_ms": {"seeds_score_best_traceback": round(phase[0], 3),
                          "cals_and_join": round(phase[1], 3),
-                         "long_score_and_best": round(phase[2], 3),
+                         "long_best_window": round(phase[2], 3),
                          "long_traceback": round(phase[3], 3),
                          "junction_detect": round(phase[4], 4)},
+            "reads_with_one_window": sole_reads,
+            "long_best_window_note": "reads with one joined window take it without a score "
+                                     "pass; the windows of the others are scored, best per "
+                                     "read, merged",
+            "long_score_windows": int(multi.sum()),
             "long_score_cells": long_cells,
             "long_score_gcups": round(long_cells / (phase[2] / 1e3) / 1e9, 1),
             "long_traceback_cells": tb_cells,

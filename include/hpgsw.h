@@ -187,6 +187,32 @@ sw_status sw_best_per_read(sw_ctx *ctx, const sw_batch *batch, const sw_hit *d_h
 sw_status sw_select_windows(sw_ctx *ctx, const sw_batch *batch, const uint32_t *d_pair_ids,
                             uint32_t n, sw_window *d_win_out, void *stream);
 
+/* Reads with a single candidate (Sec. 2, stage E tasks iii-iv: a read's best
+ * window is the best-scoring of its candidates, so a read with one candidate
+ * needs no score pass to pick it; its alignment gives its score).
+ * A pair "scores" when sw_batch_score would align it or answer it with 0:
+ * read id below n_reads and the read inside the packed reads (an empty or
+ * clipped window counts; pairs at or beyond batch->d_n_pairs do not).  For
+ * every read r < n_reads: d_sole[r] = the index of r's scoring pair when the
+ * batch holds exactly one, else 0xFFFFFFFF.  The scoring pairs of the reads
+ * with two or more are compacted in pair order into d_win_out and d_ids_out
+ * (their index in `batch`), *d_n_out = their number; both arrays must hold
+ * n_pairs entries.  Scoring that list (sw_batch.d_n_pairs = d_n_out), taking
+ * its best pair per read (sw_best_per_read) and merging (sw_merge_best) gives
+ * the best pairs sw_best_per_read gives over the whole batch (ties keep the
+ * lowest pair index in both).  Device arrays; d_sole[n_reads]. */
+sw_status sw_sole_windows(sw_ctx *ctx, const sw_batch *batch, uint32_t *d_sole,
+                          sw_window *d_win_out, uint32_t *d_ids_out, uint32_t *d_n_out,
+                          void *stream);
+
+/* For r < n_reads: d_best_pair[r] = d_sole[r] when it is not 0xFFFFFFFF, else
+ * d_ids[d_sub_best[r]] when d_sub_best[r] < n_ids, else 0xFFFFFFFF.  d_sole and
+ * d_ids as written by sw_sole_windows, d_sub_best by sw_best_per_read over its
+ * compacted list; n_ids = that list's capacity.  Device arrays. */
+sw_status sw_merge_best(sw_ctx *ctx, uint32_t n_reads, const uint32_t *d_sole,
+                        const uint32_t *d_sub_best, const uint32_t *d_ids, uint32_t n_ids,
+                        uint32_t *d_best_pair, void *stream);
+
 /* Full alignments with CIGAR for the pairs listed in d_pair_ids[n_sel]
  * (Sec. 2, stage E task iii: the alignment and its start position, which the
  * junction search of task iv reads).  d_aln[n_sel] receives coordinates;

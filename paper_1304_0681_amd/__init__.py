@@ -108,6 +108,8 @@ def lib() -> ctypes.CDLL:
         L.sw_batch_traceback.argtypes = [P, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scoring),
                                          P, U32, P, P, U32, P, P]
         L.sw_select_windows.argtypes = [P, ctypes.POINTER(sw_batch), P, U32, P, P]
+        L.sw_sole_windows.argtypes = [P, ctypes.POINTER(sw_batch), P, P, P, P, P]
+        L.sw_merge_best.argtypes = [P, U32, P, P, P, U32, P, P]
         L.sw_cigar_string.argtypes = [P, U32, ctypes.c_char_p, U32]
         L.sw_timing_enable.argtypes = [P, ctypes.c_int]
         L.sw_ctx_set_option.argtypes = [P, ctypes.c_int, ctypes.c_int]
@@ -150,6 +152,7 @@ def lib() -> ctypes.CDLL:
         for f in ("sw_ctx_create", "sw_ctx_destroy", "sw_pack2b", "sw_batch_score",
                   "sw_batch_score_noalloc",
                   "sw_best_per_read", "sw_batch_traceback", "sw_select_windows", "sw_cigar_string",
+                  "sw_sole_windows", "sw_merge_best",
                   "sw_timing_enable", "sw_timing_get", "sw_ctx_set_option", "sw_mlp_create",
                   "sw_graph_begin", "sw_graph_end", "sw_graph_launch", "sw_graph_destroy",
                   "sw_autotune", "sw_autotune_cached",
@@ -218,6 +221,16 @@ def sw_best_per_read(ctx, batch, d_hits, t_map, d_best_pair, d_best_score, d_map
 def sw_select_windows(ctx, batch, d_pair_ids, n, d_win_out, stream=None):
     _check(ctx, lib().sw_select_windows(ctx, ctypes.byref(batch.c), _ptr(d_pair_ids), int(n),
                                         _ptr(d_win_out), _stream_ptr(stream)))
+
+
+def sw_sole_windows(ctx, batch, d_sole, d_win_out, d_ids_out, d_n_out, stream=None):
+    _check(ctx, lib().sw_sole_windows(ctx, ctypes.byref(batch.c), _ptr(d_sole), _ptr(d_win_out),
+                                      _ptr(d_ids_out), _ptr(d_n_out), _stream_ptr(stream)))
+
+
+def sw_merge_best(ctx, n_reads, d_sole, d_sub_best, d_ids, n_ids, d_best_pair, stream=None):
+    _check(ctx, lib().sw_merge_best(ctx, int(n_reads), _ptr(d_sole), _ptr(d_sub_best), _ptr(d_ids),
+                                    int(n_ids), _ptr(d_best_pair), _stream_ptr(stream)))
 
 
 def sw_batch_traceback(ctx, batch, scoring, d_pair_ids, n_sel, d_aln, d_ops, ops_stride,

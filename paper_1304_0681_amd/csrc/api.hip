@@ -63,6 +63,9 @@ struct sw_ctx {
     // seeker scratch: scan tile sums, per-read region counts
     void *seek = nullptr;
     size_t seek_bytes = 0;
+    // single-window split scratch: per-read words, keep flags, scan words
+    void *sole = nullptr;
+    size_t sole_bytes = 0;
     ClassShape shapes[kNumClasses];
     int blocks_per_cu[kNumClasses];
     ClassEdges edges;    // query-length class bounds of the score path
@@ -290,6 +293,7 @@ sw_status sw_ctx_destroy(sw_ctx *ctx)
     if (ctx->seg) keep(hipFree(ctx->seg));
     if (ctx->join) keep(hipFree(ctx->join));
     if (ctx->seek) keep(hipFree(ctx->seek));
+    if (ctx->sole) keep(hipFree(ctx->sole));
     for (auto &ev : ctx->ev)
         if (ev) keep(hipEventDestroy(ev));
     delete ctx;
@@ -488,6 +492,55 @@ sw_status sw_best_per_read(sw_ctx *ctx, const sw_batch *b, const sw_hit *d_hits,
     ctx->keys_n = have / 8;
     HIP_TRY(ctx, launch_best(*b, d_hits, ctx->keys, t_map, d_best_pair, d_best_score, d_mapped,
                              static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_sole_windows(sw_ctx *ctx, const sw_batch *b, uint32_t *d_sole, sw_window *d_win_out,
+                          uint32_t *d_ids_out, uint32_t *d_n_out, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    sw_status st = check_batch(ctx, b);
+    if (st)
+        return st;
+    if (!d_n_out || (b->n_reads && !d_sole) || (b->n_pairs && (!d_win_out || !d_ids_out)))
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const size_t o_keep = align_up(8ull * std::max<uint32_t>(b->n_reads, 1));
+    const size_t o_scan = o_keep + align_up(std::max<uint32_t>(b->n_pairs, 1));
+    const size_t need = o_scan + align_up(4 * compact_scratch_words(b->n_pairs));
+    void *buf = ctx->sole;
+    size_t have = ctx->sole_bytes;
+    if ((st = ensure(ctx, &buf, &have, need)))
+        return st;
+    ctx->sole = buf;
+    ctx->sole_bytes = have;
+    char *p = static_cast<char *>(buf);
+    uint64_t *keys = reinterpret_cast<uint64_t *>(p);
+    uint8_t *keep = reinterpret_cast<uint8_t *>(p + o_keep);
+    uint32_t *scan = reinterpret_cast<uint32_t *>(p + o_scan);
+    if (b->n_reads)
+        HIP_TRY(ctx, launch_sole_windows(*b, keys, keep, d_sole, s));
+    // with no reads no pair scores: the compaction of nothing writes the zero count
+    HIP_TRY(ctx, compact_pairs(b->n_reads ? b->n_pairs : 0, keep, b->d_win, d_win_out, d_ids_out,
+                               d_n_out, scan, s));
+    return SW_OK;
+}
+
+sw_status sw_merge_best(sw_ctx *ctx, uint32_t n_reads, const uint32_t *d_sole,
+                        const uint32_t *d_sub_best, const uint32_t *d_ids, uint32_t n_ids,
+                        uint32_t *d_best_pair, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, SW_E_INVALID, "ctx is NULL");
+    if (n_reads == 0)
+        return SW_OK;
+    if (!d_sole || !d_sub_best || !d_best_pair || (n_ids && !d_ids))
+        return fail(ctx, SW_E_INVALID, "NULL buffer");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_merge_best(n_reads, d_sole, d_sub_best, d_ids, n_ids, d_best_pair,
+                                   static_cast<hipStream_t>(stream)));
     return SW_OK;
 }
 

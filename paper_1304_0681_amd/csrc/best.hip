@@ -8,6 +8,8 @@ namespace hpgsw {
 
 namespace {
 
+constexpr uint32_t kNoPair = 0xFFFFFFFFu;
+
 __global__ void __launch_bounds__(256) k_best_init(uint32_t n_reads, uint64_t *keys)
 {
     for (uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x; r < n_reads;
@@ -65,6 +67,64 @@ __global__ void __launch_bounds__(256) k_select_windows(uint32_t n, const uint32
     }
 }
 
+// Reads with a single scoring pair.  A pair scores when its read id is in
+// range and the read lies inside the packed reads (the rule of the bucketing
+// pass; empty windows score 0 and count).  Per read, one 64-bit word gathers
+// the number of scoring pairs (low half) and the sum of their indices (high
+// half), which is the pair itself when the count is one; the count stays far
+// below 2^32, so the halves never carry into each other.
+__device__ __forceinline__ bool scores(const sw_batch &b, uint32_t p, uint32_t &rid)
+{
+    rid = b.d_win[p].read_id;
+    return rid < b.n_reads && b.d_read_off[rid] + b.d_read_len[rid] <= b.reads_len;
+}
+
+__global__ void __launch_bounds__(256) k_sole_count(sw_batch b, uint64_t *keys)
+{
+    const uint32_t n_pairs = b.d_n_pairs ? min(b.n_pairs, *b.d_n_pairs) : b.n_pairs;
+    for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < n_pairs;
+         p += (uint64_t)gridDim.x * 256) {
+        uint32_t rid;
+        if (scores(b, (uint32_t)p, rid))
+            atomicAdd(reinterpret_cast<unsigned long long *>(keys + rid),
+                      (unsigned long long)((p << 32) | 1ull));
+    }
+}
+
+// keep[p]: a scoring pair of a read with two or more (over all n_pairs
+// entries, so that the compaction can run over the host count)
+__global__ void __launch_bounds__(256) k_sole_keep(sw_batch b, const uint64_t *keys, uint8_t *keep)
+{
+    const uint32_t n_valid = b.d_n_pairs ? min(b.n_pairs, *b.d_n_pairs) : b.n_pairs;
+    for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < b.n_pairs;
+         p += (uint64_t)gridDim.x * 256) {
+        uint32_t rid;
+        keep[p] = (p < n_valid && scores(b, (uint32_t)p, rid) && (uint32_t)keys[rid] >= 2u) ? 1 : 0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sole_final(uint32_t n_reads, const uint64_t *keys,
+                                                    uint32_t *sole)
+{
+    for (uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x; r < n_reads;
+         r += (uint64_t)gridDim.x * 256) {
+        const uint64_t k = keys[r];
+        sole[r] = (uint32_t)k == 1u ? (uint32_t)(k >> 32) : kNoPair;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_merge_best(uint32_t n_reads, const uint32_t *sole,
+                                                    const uint32_t *sub_best, const uint32_t *ids,
+                                                    uint32_t n_ids, uint32_t *best_pair)
+{
+    for (uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x; r < n_reads;
+         r += (uint64_t)gridDim.x * 256) {
+        const uint32_t s = sole[r];
+        const uint32_t q = sub_best[r];
+        best_pair[r] = s != kNoPair ? s : (q < n_ids ? ids[q] : kNoPair);
+    }
+}
+
 unsigned grid_for(uint64_t n)
 {
     uint64_t b = (n + 255) / 256;
@@ -93,6 +153,28 @@ hipError_t launch_select_windows(const sw_batch &b, const uint32_t *ids, uint32_
     if (n)
         hipLaunchKernelGGL(k_select_windows, dim3(grid_for(n)), dim3(256), 0, st, n, ids, b.d_win,
                            b.n_pairs, b.d_n_pairs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sole_windows(const sw_batch &b, uint64_t *keys, uint8_t *keep, uint32_t *sole,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_best_init, dim3(grid_for(b.n_reads)), dim3(256), 0, st, b.n_reads, keys);
+    if (b.n_pairs) {
+        hipLaunchKernelGGL(k_sole_count, dim3(grid_for(b.n_pairs)), dim3(256), 0, st, b, keys);
+        hipLaunchKernelGGL(k_sole_keep, dim3(grid_for(b.n_pairs)), dim3(256), 0, st, b, keys, keep);
+    }
+    hipLaunchKernelGGL(k_sole_final, dim3(grid_for(b.n_reads)), dim3(256), 0, st, b.n_reads, keys,
+                       sole);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_best(uint32_t n_reads, const uint32_t *sole, const uint32_t *sub_best,
+                             const uint32_t *ids, uint32_t n_ids, uint32_t *best_pair,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_merge_best, dim3(grid_for(n_reads)), dim3(256), 0, st, n_reads, sole,
+                       sub_best, ids, n_ids, best_pair);
     return hipGetLastError();
 }
 

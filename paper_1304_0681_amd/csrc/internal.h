@@ -119,6 +119,13 @@ hipError_t launch_best(const sw_batch &b, const sw_hit *hits, uint64_t *keys, in
                        uint32_t *best_pair, int32_t *best_score, uint8_t *mapped, hipStream_t st);
 hipError_t launch_select_windows(const sw_batch &b, const uint32_t *ids, uint32_t n, sw_window *out,
                                  hipStream_t st);
+// Per read: its only scoring pair or none (sole), and keep flags for the pairs
+// of reads with several; keys: n_reads words of scratch.
+hipError_t launch_sole_windows(const sw_batch &b, uint64_t *keys, uint8_t *keep, uint32_t *sole,
+                               hipStream_t st);
+hipError_t launch_merge_best(uint32_t n_reads, const uint32_t *sole, const uint32_t *sub_best,
+                             const uint32_t *ids, uint32_t n_ids, uint32_t *best_pair,
+                             hipStream_t st);
 int traceback_waves_per_block();
 // Query-length class bounds of the traceback (its own above 512 bases).
 ClassEdges traceback_edges();

@@ -13,7 +13,9 @@ device buffers and no host round trip:
              intron) into windows of the long reads (sw_join_cals, tasks i, ii)
   alignment  every long read against its joined windows (sw_batch_score with
              a gap extension of 0, so that an intron costs one gap open), the
-             best window per read and its alignment (task iii)
+             best window per read and its alignment (task iii); a read with
+             one joined window (most of them) skips the score pass
+             (sw_sole_windows, sw_merge_best)
   junctions  deletion runs of at least min_intron bases with an intron motif
              become N ops and are counted in a device hash table that
              accumulates over batches (sw_detect_junctions, task iv)
@@ -32,7 +34,7 @@ import numpy as np
 from . import (SW_OPT_TB_SCRATCH_MB, SW_WANT_ENDS, DeviceBatch, _ptr, aln_to_numpy,
                sw_batch_score, sw_batch_traceback, sw_best_per_read, sw_ctx_set_option,
                sw_detect_junctions, sw_join_cals, sw_junctions_clear, sw_list_junctions,
-               sw_seed_cals, junctions_to_numpy)
+               sw_merge_best, sw_seed_cals, sw_sole_windows, junctions_to_numpy)
 from .pipeline import AlignPass
 
 SEED_SCORING = (5, -4, -10, -1)
@@ -74,6 +76,14 @@ class SplicedPass:
         self.n_win = torch.zeros(1, dtype=torch.int32, device=dev)
         self.long_view = long_db.view(self.win, n_seeds, self.n_win)
         self.hits = torch.empty((max(n_seeds, 1), 3), dtype=torch.int32, device=dev)
+        # reads with one joined window go straight to the traceback; the windows
+        # of the others are scored to pick each read's best
+        self.sole = torch.empty(max(n_long, 1), dtype=torch.int32, device=dev)
+        self.multi_win = torch.empty(max(n_seeds, 1) * 12, dtype=torch.uint8, device=dev)
+        self.multi_ids = torch.empty(max(n_seeds, 1), dtype=torch.int32, device=dev)
+        self.n_multi = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.multi_view = long_db.view(self.multi_win, n_seeds, self.n_multi)
+        self.multi_best = torch.empty(n_long, dtype=torch.int32, device=dev)
         self.best_pair = torch.empty(n_long, dtype=torch.int32, device=dev)
         self.best_score = torch.empty(n_long, dtype=torch.int32, device=dev)
         self.aln = torch.empty((n_long, 7), dtype=torch.int32, device=dev)
@@ -98,12 +108,25 @@ class SplicedPass:
         sw_join_cals(self.ctx, self.cals, self.n_seeds, self.n_long, self.long_db.ref_len,
                      self.ext, self.max_gap, self.win, self.n_win, stream)
 
-    def run_long(self, stream=None):
-        sw_batch_score(self.ctx, self.long_view, self.long_scoring, 0, self.hits, stream)
-        sw_best_per_read(self.ctx, self.long_view, self.hits, self.min_score, self.best_pair,
+    def run_long_best(self, stream=None):
+        """Best joined window of every read.  A read with one window has it
+        (the traceback then finds its score); the windows of the others are
+        scored and their best merged in."""
+        sw_sole_windows(self.ctx, self.long_view, self.sole, self.multi_win, self.multi_ids,
+                        self.n_multi, stream)
+        sw_batch_score(self.ctx, self.multi_view, self.long_scoring, 0, self.hits, stream)
+        sw_best_per_read(self.ctx, self.multi_view, self.hits, self.min_score, self.multi_best,
                          self.best_score, None, stream)
+        sw_merge_best(self.ctx, self.n_long, self.sole, self.multi_best, self.multi_ids,
+                      self.n_seeds, self.best_pair, stream)
+
+    def run_long_traceback(self, stream=None):
         sw_batch_traceback(self.ctx, self.long_view, self.long_scoring, self.best_pair,
                            self.n_long, self.aln, self.ops, self.ops_stride, stream)
+
+    def run_long(self, stream=None):
+        self.run_long_best(stream)
+        self.run_long_traceback(stream)
 
     def run_junctions(self, stream=None):
         sw_detect_junctions(self.ctx, self.long_view, self.best_pair, self.n_long, self.aln,
@@ -134,10 +157,14 @@ class SplicedPass:
         return np.sort(j, order=("start", "end", "strand"))
 
     def results(self):
-        """(best_pair, best_score, aln, ops, junctions per read) of the long reads."""
-        return (self.best_pair.cpu().numpy().view(np.uint32), self.best_score.cpu().numpy(),
-                aln_to_numpy(self.aln), self.ops.cpu().numpy().view(np.uint32),
-                self.n_junc.cpu().numpy().view(np.uint32))
+        """(best_pair, best_score, aln, ops, junctions per read) of the long reads
+        (a read with one window has its alignment's score as best score)."""
+        aln = aln_to_numpy(self.aln)
+        bs = self.best_score.cpu().numpy()
+        sole = self.sole.cpu().numpy()[:self.n_long] != -1
+        bs[sole] = aln["score"][sole]
+        return (self.best_pair.cpu().numpy().view(np.uint32), bs, aln,
+                self.ops.cpu().numpy().view(np.uint32), self.n_junc.cpu().numpy().view(np.uint32))
 
 
 class SeekerSplicedPass(SplicedPass):

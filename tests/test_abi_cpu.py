@@ -33,6 +33,8 @@ def test_null_and_invalid_arguments():
     assert L.sw_batch_traceback(None, None, None, None, 0, None, None, 0, None, None) == sw.SW_E_INVALID
     assert L.sw_pack2b(None, None, 0, None, None, None) == sw.SW_E_INVALID
     assert L.sw_select_windows(None, None, None, 0, None, None) == sw.SW_E_INVALID
+    assert L.sw_sole_windows(None, None, None, None, None, None, None) == sw.SW_E_INVALID
+    assert L.sw_merge_best(None, 4, None, None, None, 0, None, None) == sw.SW_E_INVALID
     assert L.sw_ctx_destroy(None) == sw.SW_E_INVALID
 
 

@@ -357,3 +357,118 @@ def test_spliced_pass_from_seeker_vs_oracle(ctx, spliced_long):
     assert got == want["table"]
     truth_j = {(int(a), int(b), int(s)) for a, b, s in truth["junctions"]}
     assert len(set(got) & truth_j) >= 0.8 * len(truth_j), (len(set(got) & truth_j), len(truth_j))
+
+
+def _sole_expected(win, n_valid, read_off, read_len, reads_len):
+    """sw_sole_windows by its definition: a pair scores when it lies below the
+    device count, its read id is in range and the read lies inside the packed
+    reads; a read with exactly one scoring pair has it as sole pair, the
+    scoring pairs of the other reads form the list, in pair order."""
+    n_reads = len(read_len)
+    scoring = [p < n_valid and int(w["read_id"]) < n_reads and
+               int(read_off[int(w["read_id"])]) + int(read_len[int(w["read_id"])]) <= reads_len
+               for p, w in enumerate(win)]
+    per = {}
+    for p, ok in enumerate(scoring):
+        if ok:
+            per.setdefault(int(win[p]["read_id"]), []).append(p)
+    sole = np.full(n_reads, 0xFFFFFFFF, np.uint32)
+    for r, ps in per.items():
+        if len(ps) == 1:
+            sole[r] = ps[0]
+    ids = [p for p, ok in enumerate(scoring) if ok and len(per[int(win[p]["read_id"])]) >= 2]
+    return sole, np.array(ids, np.uint32)
+
+
+def test_sole_windows_and_merge_equal_best_over_all_pairs(ctx):
+    """Edge cases of the single-window split: reads with no, one and several
+    windows (interleaved with other reads' windows), empty and clipped windows,
+    an empty read, read ids out of range, a read outside the packed reads, and
+    a device count that cuts the list; then score -> best -> merge over the
+    compacted list against sw_best_per_read over the whole batch and against
+    the oracle's best pairs."""
+    rng = np.random.default_rng(91)
+    ref = rng.integers(0, 4, 6000).astype(np.uint8)
+    lens = [60, 80, 70, 50, 90, 0, 75, 40, 65, 30]
+    planted = {1: 1250, 6: 4550}     # reads copied from inside their second window
+    reads, off = [], []
+    o = 0
+    for r, n in enumerate(lens):
+        q = ref[planted[r]:planted[r] + n] if r in planted else rng.integers(0, 4, n).astype(np.uint8)
+        reads.append(synth.ASCII[q].tobytes())
+        off.append(o)
+        o += n
+    read_off = np.array(off, np.uint64)
+    read_len = np.array(lens, np.uint16)
+    read_off[9] = o - 10           # read 9 (30 bases) lies partly outside the packed reads
+    W = [  # (read, ref_begin, len, strand)
+        (0, 100, 300, 1),                          # read 0: one window
+        (1, 500, 250, 0), (3, 900, 0, 0),          # read 3: one empty window
+        (1, 1200, 300, 0), (99, 10, 100, 0),       # read id out of range
+        (4, 5900, 300, 1), (4, 2000, 200, 0),      # read 4: one window clipped at the end
+        (5, 3000, 200, 0),                         # read 5: empty read, one window
+        (1, 3500, 280, 1), (6, 4000, 300, 0),      # read 1: three windows, interleaved
+        (6, 4500, 250, 0), (9, 100, 200, 0),       # read 9: outside the packed reads
+        (8, 6500, 100, 0),                         # read 8: starts past the reference
+        (7, 200, 300, 0), (7, 700, 300, 1),        # read 7: its second window is cut by the count
+    ]
+    win = np.zeros(len(W), sw.WINDOW_DTYPE)
+    for k, w in enumerate(W):
+        win[k] = w + (0,)
+    ascii_reads = np.frombuffer(b"".join(reads), np.uint8)
+    ref_ascii = synth.ASCII[ref]
+    db = sw.DeviceBatch(ctx, ref_ascii, ascii_reads, read_off, read_len, win)
+    n_valid = len(W) - 1
+    d_n = torch.tensor([n_valid], dtype=torch.int32, device="cuda")
+    full = db.view(db.win, len(W), d_n)
+    nr = len(lens)
+    sole = torch.full((nr,), -7, dtype=torch.int32, device="cuda")
+    mwin = torch.zeros(len(W) * 12, dtype=torch.uint8, device="cuda")
+    mids = torch.full((len(W),), -7, dtype=torch.int32, device="cuda")
+    n_out = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    sw.sw_sole_windows(ctx, full, sole, mwin, mids, n_out)
+    torch.cuda.synchronize()
+    want_sole, want_ids = _sole_expected(win, n_valid, read_off, read_len, len(ascii_reads))
+    assert (sole.cpu().numpy().view(np.uint32) == want_sole).all()
+    k = int(n_out.item())
+    assert k == len(want_ids) == 7
+    assert (mids.cpu().numpy().view(np.uint32)[:k] == want_ids).all()
+    assert (mwin.cpu().numpy().view(sw.WINDOW_DTYPE)[:k] == win[want_ids]).all()
+    assert list(want_sole[[0, 3, 5, 7, 8]]) == [0, 2, 7, 13, 12]
+    assert (want_sole[[1, 2, 4, 6, 9]] == 0xFFFFFFFF).all()
+    # score -> best over the list -> merge, against best over all pairs
+    hits_all = torch.empty((len(W), 3), dtype=torch.int32, device="cuda")
+    bp_all = torch.empty(nr, dtype=torch.int32, device="cuda")
+    bs_all = torch.empty(nr, dtype=torch.int32, device="cuda")
+    sw.sw_batch_score(ctx, full, SEED_SCORING, 0, hits_all)
+    sw.sw_best_per_read(ctx, full, hits_all, 0, bp_all, bs_all)
+    mv = db.view(mwin, len(W), n_out)
+    hits = torch.empty((len(W), 3), dtype=torch.int32, device="cuda")
+    sub = torch.empty(nr, dtype=torch.int32, device="cuda")
+    sub_s = torch.empty(nr, dtype=torch.int32, device="cuda")
+    sw.sw_batch_score(ctx, mv, SEED_SCORING, 0, hits)
+    sw.sw_best_per_read(ctx, mv, hits, 0, sub, sub_s)
+    best = torch.full((nr,), -7, dtype=torch.int32, device="cuda")
+    sw.sw_merge_best(ctx, nr, sole, sub, mids, len(W), best)
+    torch.cuda.synchronize()
+    got = best.cpu().numpy().view(np.uint32)
+    assert (got == bp_all.cpu().numpy().view(np.uint32)).all()
+    # the oracle's best pairs over the scoring pairs below the count
+    ok = np.array([p for p in range(n_valid) if int(win[p]["read_id"]) < nr and p != 11])
+    ob = synth.Batch(ref=ref_ascii, reads=ascii_reads, read_off=read_off, read_len=read_len,
+                     windows=win[ok], truth={})
+    res, _ = oracle.align_batch(ob, SEED_SCORING, mode=0)
+    ep, _ = oracle.best_per_read(res["score"], win["read_id"][ok].astype(np.int64), nr)
+    ep = np.where(ep != 0xFFFFFFFF, ok[np.minimum(ep, len(ok) - 1)], 0xFFFFFFFF).astype(np.uint32)
+    assert (got == ep).all()
+    assert got[1] == 3 and got[6] == 10          # the planted windows win
+    # empty batches: no pairs, and no reads
+    sw.sw_sole_windows(ctx, db.view(mwin, 0), sole, mwin, mids, n_out)
+    torch.cuda.synchronize()
+    assert int(n_out.item()) == 0 and (sole.cpu().numpy() == -1).all()
+    nb = db.view(db.win, len(W))
+    nb.c.n_reads = 0
+    n_out.fill_(-7)
+    sw.sw_sole_windows(ctx, nb, sole, mwin, mids, n_out)
+    torch.cuda.synchronize()
+    assert int(n_out.item()) == 0
