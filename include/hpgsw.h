@@ -549,7 +549,7 @@ sw_status sw_mlp_train_step(sw_ctx *ctx, sw_mlp *mlp, const uint16_t *d_x, const
 
 /* Training labels from plain scores: d_y[p] = 1 if score(p) >= best score of
  * its read - margin and that best score is >= min_best (d_best_score from
- * sw_best_per_read), else 0.  min_best = INT32_MIN gives the plain margin label;
+ * sw_best_per_read), else 0 (also for a pair whose read id is out of range).  min_best = INT32_MIN gives the plain margin label;
  * min_best = the mapping threshold labels only candidates that can become the
  * record of a mapped read (stage E task iv), which is what a rule that may skip
  * predicted-unmapped reads needs. */

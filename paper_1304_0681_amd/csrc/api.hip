@@ -1510,7 +1510,7 @@ sw_status sw_mlp_labels(sw_ctx *ctx, const sw_batch *b, const sw_hit *d_hits,
     if (!d_hits || !d_best_score || !d_y)
         return fail(ctx, SW_E_INVALID, "NULL buffer");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    HIP_TRY(ctx, mlp_labels(b->n_pairs, b->d_win, d_hits, d_best_score, margin, min_best, d_y,
+    HIP_TRY(ctx, mlp_labels(b->n_pairs, b->d_win, b->n_reads, d_hits, d_best_score, margin, min_best, d_y,
                             static_cast<hipStream_t>(stream)));
     return SW_OK;
 }

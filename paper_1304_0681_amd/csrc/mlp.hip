@@ -370,15 +370,18 @@ __global__ void __launch_bounds__(256) k_cast_params(const float *theta, MlpDev 
 // Labels, read segments, filter decision, compaction.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_labels(uint32_t n_pairs, const sw_window *win,
-                                                const sw_hit *hits, const int32_t *best,
-                                                int32_t margin, int32_t min_best, float *y)
+                                                uint32_t n_reads, const sw_hit *hits,
+                                                const int32_t *best, int32_t margin,
+                                                int32_t min_best, float *y)
 {
     const uint32_t p = blockIdx.x * 256 + threadIdx.x;
     if (p >= n_pairs)
         return;
     const int s = hits[p].score;
-    const int bs = best[win[p].read_id];
-    y[p] = (s >= 0 && s >= bs - margin && bs >= min_best) ? 1.f : 0.f;
+    const uint32_t r = win[p].read_id;
+    // a pair of no read scores -1 and is labelled 0 without a best score
+    const int bs = r < n_reads ? best[r] : 0;
+    y[p] = (r < n_reads && s >= 0 && s >= bs - margin && bs >= min_best) ? 1.f : 0.f;
 }
 
 __global__ void __launch_bounds__(256) k_seg_init(uint32_t n_reads, uint32_t *first, uint32_t *last,
@@ -698,12 +701,12 @@ hipError_t mlp_adam(float *theta, float *m, float *v, const float *g, float lr, 
     return hipGetLastError();
 }
 
-hipError_t mlp_labels(uint32_t n_pairs, const sw_window *win, const sw_hit *hits,
+hipError_t mlp_labels(uint32_t n_pairs, const sw_window *win, uint32_t n_reads, const sw_hit *hits,
                       const int32_t *best, int32_t margin, int32_t min_best, float *y, hipStream_t st)
 {
     if (n_pairs)
-        hipLaunchKernelGGL(k_labels, dim3(blocks_for(n_pairs)), dim3(256), 0, st, n_pairs, win, hits,
-                           best, margin, min_best, y);
+        hipLaunchKernelGGL(k_labels, dim3(blocks_for(n_pairs)), dim3(256), 0, st, n_pairs, win,
+                           n_reads, hits, best, margin, min_best, y);
     return hipGetLastError();
 }
 

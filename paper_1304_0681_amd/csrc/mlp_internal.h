@@ -35,8 +35,9 @@ hipError_t mlp_backprop(const MlpDev &W, const uint16_t *X, const float *y, uint
 size_t mlp_workspace_bytes(uint32_t B);
 hipError_t mlp_adam(float *theta, float *m, float *v, const float *g, float lr, int step,
                     hipStream_t st);
-hipError_t mlp_labels(uint32_t n_pairs, const sw_window *win, const sw_hit *hits,
-                      const int32_t *best, int32_t margin, int32_t min_best, float *y, hipStream_t st);
+hipError_t mlp_labels(uint32_t n_pairs, const sw_window *win, uint32_t n_reads, const sw_hit *hits,
+                      const int32_t *best, int32_t margin, int32_t min_best, float *y,
+                      hipStream_t st);
 hipError_t read_segments(uint32_t n_pairs, const uint32_t *d_n, const sw_window *win,
                          uint32_t n_reads, uint32_t *first, uint32_t *last, uint32_t *count,
                          hipStream_t st);

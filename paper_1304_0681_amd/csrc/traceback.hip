@@ -184,7 +184,9 @@ __global__ void __launch_bounds__(64 * kWaves, tb_min_waves<RPL>()) k_sw_traceba
                 P.aln[k_sel] = sw_aln{-1, -1, -1, -1, -1, 0u, 4u};
             continue;
         }
-        const uint32_t pair = P.sel[k_sel];
+        // an idle group reads window 0 (the batch has pairs): the caller's ids may
+        // name no pair (e.g. 0xFFFFFFFF for a read without a hit), the first one too
+        const uint32_t pair = active ? P.sel[k_sel] : 0u;
         const sw_window w = P.win[pair];
         int m = 0, n = 0, c_lo = 0;
         uint64_t roff = 0;

@@ -301,6 +301,35 @@ def test_invalid_and_empty_pairs(ctx):
     assert_aln_equal(a, o, ref_r, rops)
 
 
+def test_traceback_ids_naming_no_pair_come_first(ctx):
+    """Selected ids that name no pair (0xFFFFFFFF, as sw_best_per_read gives a read
+    without a hit, and the batch's pair count), the first id among them, next to
+    a few real pairs of several query-length classes, so that each class's last
+    wave has idle lane groups: those read a window of the batch, never one at a
+    stray id.  Real pairs equal the oracle; the others are marked invalid."""
+    g = np.random.default_rng(41)
+    refc = g.integers(0, 4, 20_000).astype(np.uint8)
+    reads, wins = [], []
+    for m in (30, 100, 150, 600):
+        for _ in range(3):
+            b0 = int(g.integers(0, 19_000 - m))
+            seg = refc[b0 + 40:b0 + 40 + m].copy()
+            mut = g.random(m) < 0.03
+            seg[mut] = (seg[mut] + 1) % 4
+            reads.append(synth.ASCII[seg].tobytes())
+            wins.append((len(reads) - 1, b0, m + 80, 0))
+    b = synth.custom(synth.ASCII[refc].tobytes(), reads, wins)
+    none = 0xFFFFFFFF
+    sel = np.array([none, 0, 1, none, 3, b.n_pairs, 4, 6, 7, 9, 10, 11, none], dtype=np.uint32)
+    real = sel < b.n_pairs
+    ref, rops = oracle.align_batch(b, SC, mode=1, sel=sel[real])
+    for band in (False, True):
+        a, o = gpu_traceback(ctx, b, sel=sel, band=band)
+        assert_aln_equal(a[real], o[real], ref, rops)
+        for k in np.nonzero(~real)[0]:
+            assert (int(a[k]["score"]), int(a[k]["n_ops"]), int(a[k]["status"])) == (-1, 0, 2), k
+
+
 def test_traceback_truncation(ctx):
     # 2S3M1D5M2S: five ops, cut to the first two
     b = synth.custom(b"TTACGTTACGTGG", [b"CCACGTACGTAA"], [(0, 0, 13, 0)])
