@@ -130,11 +130,14 @@ __device__ __forceinline__ uint32_t tb_window_word(const TBParams &P, int64_t rb
 
 // STRIP: queries longer than one strip of G*RPL rows (G == 64); the boundary
 // row between strips goes through the tail of the pair's slot.
-// Waves per SIMD: the 13- and 20-row tiles (100- and 150-nt queries) are held to
-// 168 VGPRs for three, the 24- and 32-row tiles to 256 for two; the 8-row tiles
-// fit four as they are.
+// Waves per SIMD: the 12-, 13-, 16- and 20-row tiles are held to 168 VGPRs for
+// three, the 32-row strip tile to 256 for two; the 8-row tiles fit four as they
+// are.
 template <int RPL>
-constexpr int tb_min_waves() { return RPL >= 24 ? 2 : (RPL == 13 || RPL == 20) ? 3 : 1; }
+constexpr int tb_min_waves()
+{
+    return RPL >= 24 ? 2 : (RPL == 12 || RPL == 13 || RPL == 16 || RPL == 20) ? 3 : 1;
+}
 
 template <int G, int RPL, bool STRIP>
 __global__ void __launch_bounds__(64 * kWaves, tb_min_waves<RPL>()) k_sw_traceback(const TBParams P)
@@ -546,11 +549,13 @@ hipError_t tb_launch(const TBParams &p, int grid, hipStream_t st)
 // Traceback shapes per query-length class (G lanes x RPL rows >= the class
 // bound).  Above 512 bases the classes differ from the score path's: a
 // 768-row tile for 513-768-base queries (a 1,024-row tile leaves a third of
-// its rows empty on them), the 1,024-row tile for 769-1,024, and strips of
-// 2,048 rows for everything longer.
+// its rows empty on them), a 1,024-row tile for 769-1,024, and strips of
+// 2,048 rows for everything longer.  From 257 bases on, a pair takes the whole
+// wave: 8, 12 or 16 rows per lane keep three or four waves per SIMD (32 lanes
+// with 16, 24 or 32 rows held two or three).
 static const ClassShape kTBShapes[kNumClasses] = {
     {16, 2, 8},   {32, 4, 8},   {64, 8, 8},    {100, 8, 13},   {128, 16, 8},  {160, 8, 20},
-    {256, 32, 8}, {512, 16, 32}, {768, 32, 24}, {1024, 32, 32}, {65535, 64, 32}};
+    {256, 32, 8}, {512, 64, 8}, {768, 64, 12}, {1024, 64, 16}, {65535, 64, 32}};
 
 ClassEdges traceback_edges()
 {
@@ -602,9 +607,9 @@ hipError_t launch_traceback_class(int cls, const sw_batch &b, const sw_scoring &
     case 4: return tb_launch<16, 8, false>(p, grid, st);
     case 5: return tb_launch<8, 20, false>(p, grid, st);
     case 6: return tb_launch<32, 8, false>(p, grid, st);
-    case 7: return tb_launch<16, 32, false>(p, grid, st);
-    case 8: return tb_launch<32, 24, false>(p, grid, st);
-    case 9: return tb_launch<32, 32, false>(p, grid, st);
+    case 7: return tb_launch<64, 8, false>(p, grid, st);
+    case 8: return tb_launch<64, 12, false>(p, grid, st);
+    case 9: return tb_launch<64, 16, false>(p, grid, st);
     default: return tb_launch<64, 32, true>(p, grid, st);
     }
 }
