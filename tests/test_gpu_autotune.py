@@ -70,7 +70,10 @@ def test_autotune_mixed_lengths_parity():
         b = synth.custom(synth.ASCII[ref].tobytes(), reads, wins)
         db = sw.DeviceBatch.from_synth(ctx, b)
         tune = sw.sw_autotune(ctx, db, SC, flags=0, repeats=1)
-        assert sum(1 for t in tune if t["path"]) >= 6
+        # how many classes the tuned bounds keep is a timing decision (adjacent
+        # classes may merge); they still hold every length of the sample
+        used = [t for t in tune if t["path"]]
+        assert len(used) >= 3 and max(t["m_max"] for t in used) >= 600
         hits = torch.empty((b.n_pairs, 3), dtype=torch.int32, device="cuda")
         sw.sw_batch_score(ctx, db, SC, 0, hits)
         torch.cuda.synchronize()
