@@ -876,7 +876,8 @@ def bench_seeker(ctx, args):
     on_origin = (src > 0) & (np.abs(rec["ref_begin"] - ori) <= 20) & real
     mapping = {
         "note": "stage B records for the reads it maps, SW alignments with CIGAR (best window, "
-                "banded traceback) for the rest, one record per read",
+                "banded traceback; a read with one window skips the score pass) for the rest, "
+                "one record per read",
         "ms_per_step": round(t_m * 1e3, 3), "reads_per_s": round(b.n_reads / t_m, 1),
         "by_stage_b": round(float((src == STAGE_B).mean()), 5),
         "by_sw": round(float((src == STAGE_E).mean()), 5),

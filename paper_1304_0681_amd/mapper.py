@@ -9,7 +9,7 @@ runs, with fixed device buffers and no host round trip:
              (sw_cal_seeker), extended and joined into windows (sw_join_cals)
   stage E    SW of those reads against their windows, the best window per read
              and its alignment with CIGAR (AlignPass with the band of the best
-             hit)
+             hit; a read with one window takes it without the score pass)
 
 results() merges the two sources into one record per read (arrays, no
 per-read host loop): the stage B record (the first of its best stratum, with
@@ -46,7 +46,7 @@ class ShortReadMapper:
         self.seeker = CandidateSeeker(ctx, db, index, max_occ=max_occ, merge_gap=merge_gap,
                                       min_len=min_len, ext=ext, max_gap=max_gap, stage_b=True)
         self.align = AlignPass(ctx, self.seeker.view, scoring, t_map=self.t_map,
-                               ops_stride=ops_stride, band=True)
+                               ops_stride=ops_stride, band=True, sole_first=True)
 
     def run(self, stream=None):
         """Stages B-E for every read (the reads are already encoded)."""

@@ -120,3 +120,51 @@ def test_graph_capture_refuses_growth(ctx):
         assert (sw.hits_to_numpy(h1)["score"] == ref["score"]).all()
     finally:
         sw.sw_ctx_destroy(ctx2)
+
+
+def test_sole_first_pass_equals_oracle(ctx, spliced):
+    """AlignPass with sole_first on seeds of which every third keeps one window,
+    every third all of them and a few none: best pairs, best scores, alignments
+    and CIGARs equal the oracle's, eagerly and over graph replays."""
+    b0 = spliced[0]
+    rid = b0.windows["read_id"].astype(np.int64)
+    first = np.ones(len(rid), bool)
+    first[1:] = rid[1:] != rid[:-1]
+    keep = (rid % 3 == 1) | ((rid % 3 == 0) & first) | ((rid % 3 == 2) & (rid % 7 != 0))
+    b = synth.Batch(ref=b0.ref, reads=b0.reads, read_off=b0.read_off, read_len=b0.read_len,
+                    windows=b0.windows[keep], truth={})
+    per = np.bincount(b.windows["read_id"].astype(np.int64), minlength=b.n_reads)
+    assert (per == 0).sum() > 20 and (per == 1).sum() > 500 and (per > 1).sum() > 500
+    ref, _ = oracle.align_batch(b, SC, mode=0)
+    ep, es = oracle.best_per_read(ref["score"], b.windows["read_id"].astype(np.int64), b.n_reads)
+    has = ep != 0xFFFFFFFF
+    ra, rops = oracle.align_batch(b, SC, mode=1, sel=ep[has])
+    db = sw.DeviceBatch.from_synth(ctx, b)
+    ap = AlignPass(ctx, db, SC, band=True, sole_first=True)
+
+    def check_sole(out):
+        gp, gs, ga, go = out
+        assert (gp == ep).all()
+        assert (gs[has] == es[has]).all() and (gs[~has] == -1).all()
+        for f in ("score", "read_begin", "read_end", "ref_begin", "ref_end", "n_ops", "status"):
+            assert (ga[f][has] == ra[f]).all(), f
+        for k, r in enumerate(np.nonzero(has)[0]):
+            n = int(ra[k]["n_ops"])
+            assert (go[r, :n] == rops[k, :n]).all(), r
+
+    ap.run()
+    torch.cuda.synchronize()
+    check_sole(ap.results())
+    s = torch.cuda.Stream()
+    ap.capture(s)
+    try:
+        for rep in range(3):
+            for t in (ap.best_pair, ap.best_score, ap.aln, ap.ops, ap.sole, ap.multi_best,
+                      ap.bbt.hits):
+                t.fill_(-3)
+            torch.cuda.synchronize()
+            ap.replay(s)
+            s.synchronize()
+            check_sole(ap.results())
+    finally:
+        ap.close()
