@@ -200,7 +200,9 @@ sw_status sw_select_windows(sw_ctx *ctx, const sw_batch *batch, const uint32_t *
  * n_pairs entries.  Scoring that list (sw_batch.d_n_pairs = d_n_out), taking
  * its best pair per read (sw_best_per_read) and merging (sw_merge_best) gives
  * the best pairs sw_best_per_read gives over the whole batch (ties keep the
- * lowest pair index in both).  Device arrays; d_sole[n_reads]. */
+ * lowest pair index in both).  Device arrays; d_sole[n_reads].  Uses context
+ * scratch (8 bytes per read and about 1 per pair; growing it fails with
+ * SW_E_STATE during capture or while a captured graph of the context lives). */
 sw_status sw_sole_windows(sw_ctx *ctx, const sw_batch *batch, uint32_t *d_sole,
                           sw_window *d_win_out, uint32_t *d_ids_out, uint32_t *d_n_out,
                           void *stream);
