@@ -1,7 +1,7 @@
-// Host stand-in for the few HIP runtime declarations the score and splice
-// kernels' sources use, so that the unmodified kernel files compile as plain
-// C++ for the CPU models (tests/host_model/score_model.cpp, splice_model.cpp
-// and seeker_model.cpp).  Kernel launches compile to nothing; the models call
+// Host stand-in for the few HIP runtime declarations the kernels' sources use,
+// so that the unmodified kernel files compile as plain C++ for the CPU models
+// (tests/host_model/score_model.cpp, splice_model.cpp, seeker_model.cpp and
+// traceback_model.cpp).  Kernel launches compile to nothing; the models call
 // the kernel functions themselves, one thread (or one loop step) per lane.
 // Cross-lane operations, barriers and the AMDGPU builtins the kernels use are
 // declared here and defined by the models.
@@ -71,3 +71,6 @@ inline int __clzll(long long x) { return x ? __builtin_clzll((unsigned long long
 #define __builtin_amdgcn_perm model_perm
 #define __builtin_amdgcn_alignbit model_alignbit
 #define __builtin_amdgcn_sbfe model_sbfe
+// v_bitop3_b32: bit k of the result is bit (a_k << 2 | b_k << 1 | c_k) of the table
+uint32_t model_bitop3(uint32_t a, uint32_t b, uint32_t c, uint32_t table);
+#define __builtin_amdgcn_bitop3_b32 model_bitop3

@@ -1,0 +1,126 @@
+"""The traceback kernel's own source, run on the CPU.
+
+tests/host_model/traceback_model.cpp compiles the unmodified kernel file
+(paper_1304_0681_amd/csrc/traceback.hip) as C++ for the host, against the
+stand-in HIP header, on the lockstep wave model (lanes as threads meeting at a
+barrier around every cross-lane operation; DPP shifts, v_bitop3_b32,
+v_alignbit_b32 and v_bfe_i32 emulated from their definitions).  It runs the
+whole-wave tiles (64 lanes per pair: 8, 12 and 16 rows per lane for queries of
+257-1,024 bases, and the strip-mined tile above that), whose cross-lane
+operations are all wave-uniform, on pairs of lengths spread over each class,
+both strands, windows at and past the reference ends, with and without the
+band of the score pass's hits, and with selected ids that name no pair placed
+first.  Every array and the code scratch lie against a guard page (after their
+end, then before their start); coordinates, scores and CIGARs must equal the
+oracle's, and nothing outside the class may be written."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HM = os.path.join(ROOT, "tests", "host_model")
+CXX = os.environ.get("HOST_CXX", "/opt/rocm/llvm/bin/clang++")
+SC = (5, -4, -10, -1)
+NONE = 0xFFFFFFFF
+ALN = np.dtype([("score", "<i4"), ("read_begin", "<i4"), ("read_end", "<i4"),
+                ("ref_begin", "<i4"), ("ref_end", "<i4"), ("n_ops", "<u4"), ("status", "<u4")])
+
+
+@pytest.fixture(scope="module")
+def model(tmp_path_factory):
+    if not os.path.exists(CXX):
+        pytest.skip("no host clang++ for the kernel model")
+    out = str(tmp_path_factory.mktemp("model") / "libtb_model.so")
+    subprocess.check_call([CXX, "-std=c++20", "-O2", "-shared", "-fPIC", "-pthread", "-w",
+                           "-I", os.path.join(HM, "hip_stub"), "-I", os.path.join(ROOT, "include"),
+                           "-I", os.path.join(ROOT, "paper_1304_0681_amd", "csrc"),
+                           os.path.join(HM, "traceback_model.cpp"), "-o", out])
+    L = ctypes.CDLL(out)
+    L.model_traceback.restype = ctypes.c_int
+    return L
+
+
+def _batch(seed, ms, ns, ref_len=40_000):
+    g = np.random.default_rng(seed)
+    ref = g.integers(0, 4, ref_len).astype(np.uint8)
+    reads, wins = [], []
+    for k, m in enumerate(ms):
+        n = ns[k % len(ns)]
+        st = k & 1
+        b0 = int(g.integers(1000, ref_len - m - 1000))
+        seg = ref[b0:b0 + m].copy()
+        mut = g.random(m) < 0.03
+        seg[mut] = (seg[mut] + 1) % 4
+        k0 = int(g.integers(20, m - 20))
+        seg = np.concatenate([seg[:k0], seg[k0 + 3:], g.integers(0, 4, 3).astype(np.uint8)])
+        reads.append(synth.ASCII[(3 - seg[::-1]) if st else seg].tobytes())
+        wins.append((len(reads) - 1, max(b0 - int(g.integers(0, max(1, n // 3))), 0), n, st))
+    wins.append((0, 0, 300, 0))                       # at the reference start
+    wins.append((1, ref_len - 150, 300, 1))           # running past its end
+    return synth.custom(synth.ASCII[ref].tobytes(), reads, wins)
+
+
+def _run(model, b, sel, ids, RPL, strip, at_end, hits, waves=2):
+    G = 64
+    m = b.read_len[b.windows["read_id"][sel[ids]]].astype(np.int64)
+    n = np.minimum(b.windows["len"][sel[ids]].astype(np.int64),
+                   len(b.ref) - b.windows["ref_begin"][sel[ids]].astype(np.int64))
+    nmax, mmax = int(n.max()), int(m.max())
+    SR = G * RPL
+    strips = (mmax + SR - 1) // SR if strip else 1
+    wpl = (RPL + 7) // 8
+    slot = strips * G * wpl * (nmax + G - 1) + (2 * nmax if strip else 0) + mmax + nmax + 8
+    ref2b = oracle.pack2b(b.ref).view(np.uint32)
+    reads2b = oracle.pack2b(b.reads).view(np.uint32)
+    win = np.ascontiguousarray(b.windows)
+    stride = mmax + nmax + 4
+    aln = np.full(len(sel), -7, ALN)
+    ops = np.full((len(sel), stride), 7, np.uint32)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    sc = np.array(SC, np.int32)
+    h = None if hits is None else np.ascontiguousarray(hits)
+    rc = model.model_traceback(RPL, int(strip), waves, int(at_end), p(ref2b), ctypes.c_uint64(len(b.ref)),
+                               p(reads2b), ctypes.c_uint64(len(reads2b)),
+                               p(np.ascontiguousarray(b.read_off, np.uint64)),
+                               p(np.ascontiguousarray(b.read_len, np.uint16)),
+                               ctypes.c_uint32(b.n_reads), p(win), ctypes.c_uint32(b.n_pairs),
+                               p(sel), ctypes.c_uint32(len(sel)), p(ids), ctypes.c_uint32(len(ids)),
+                               ctypes.c_uint32(nmax), ctypes.c_uint32(mmax), p(sc),
+                               None if h is None else p(h), ctypes.c_uint64(waves * slot),
+                               p(aln), p(ops), ctypes.c_uint32(stride))
+    assert rc == 0
+    return aln, ops
+
+
+@pytest.mark.parametrize("RPL,strip,lo,hi", [(8, False, 256, 512), (12, False, 512, 768),
+                                             (16, False, 768, 1024), (32, True, 1024, 2400)])
+def test_whole_wave_traceback_on_host_equals_oracle(model, RPL, strip, lo, hi):
+    ms = sorted({lo + 1, lo + 2, (lo + hi) // 2, hi - 1, hi} - {2400}) + ([2300] if strip else [])
+    b = _batch(500 + RPL, ms, [hi // 2, 40, hi + 200, 1000])
+    pairs = np.arange(b.n_pairs, dtype=np.uint32)
+    m = b.read_len[b.windows["read_id"]].astype(np.int64)
+    cls = pairs[(m > lo) & (m <= hi)]
+    # ids naming no pair come first in the selection; the class's pairs follow
+    sel = np.concatenate([[NONE, b.n_pairs], cls, [NONE]]).astype(np.uint32)
+    ids = np.arange(2, 2 + len(cls), dtype=np.uint32)
+    ra, rops = oracle.align_batch(b, SC, mode=1, sel=cls)
+    hits_all, _ = oracle.align_batch(b, SC, mode=0)
+    hits = np.zeros(b.n_pairs, [("score", "<i4"), ("read_end", "<i4"), ("ref_end", "<i4")])
+    for f in ("score", "read_end", "ref_end"):
+        hits[f] = hits_all[f]
+    for band, at_end in ((False, True), (True, False)):
+        aln, ops = _run(model, b, sel, ids, RPL, strip, at_end, hits if band else None)
+        got = aln[ids]
+        for f in ("score", "read_begin", "read_end", "ref_begin", "ref_end", "n_ops", "status"):
+            assert (got[f] == ra[f]).all(), (RPL, band, f, got[f], ra[f])
+        for k, i in enumerate(ids):
+            nn = int(ra[k]["n_ops"])
+            assert (ops[i, :nn] == rops[k, :nn]).all(), (RPL, band, k)
+        others = np.setdiff1d(np.arange(len(sel)), ids)
+        assert (aln["score"][others] == -7).all() and (ops[others] == 7).all()
