@@ -57,7 +57,11 @@ unsigned long long atomicCAS(unsigned long long *p, unsigned long long cmp, unsi
 uint32_t model_perm(uint32_t hi, uint32_t lo, uint32_t sel);
 uint32_t model_alignbit(uint32_t hi, uint32_t lo, uint32_t shift);
 int model_sbfe(int src, int offset, int width);
+#ifdef MODEL_FENCE_HOOK
+void __threadfence_block();     // defined by the model (it marks phases of the kernel)
+#else
 inline void __threadfence_block() {}
+#endif
 void __syncthreads();
 void model_wave_barrier();
 uint64_t __ballot(int pred);

@@ -1,6 +1,8 @@
 // Lockstep model of one AMD wave on the host (test infrastructure), for the
-// host model of the wavefront score kernels (score_model.cpp), whose cross-lane
-// operations all sit in wave-uniform control flow.  Lanes are threads.  The 64 lanes of a wave meet at a
+// host models of the wavefront score and traceback kernels (score_model.cpp,
+// traceback_model.cpp).  Cross-lane operations meet the whole wave, or, for a
+// lane whose t_group is below 64, only its lane group (a kernel whose groups
+// run divergent code that never reads across groups).  Lanes are threads.  The 64 lanes of a wave meet at a
 // barrier around every cross-lane operation (each lane publishes its value, the
 // barrier completes, each lane reads its source lane, a second barrier
 // completes): the lockstep the hardware gives.  The instructions are emulated
@@ -33,16 +35,22 @@
 
 namespace wave_model {
 
-// Sense-reversing barrier of the 64 lanes of a wave; spins, yielding the CPU,
-// since the lanes outnumber the host's cores.
+// Sense-reversing barrier of `n` lanes (the 64 of a wave, or one lane group);
+// spins, yielding the CPU, since the lanes outnumber the host's cores.
 struct LaneBarrier {
+    int n = 64;
     std::atomic<int> count{64};
     std::atomic<int> sense{0};
+    void reset(int lanes)
+    {
+        n = lanes;
+        count.store(lanes);
+    }
     void arrive_and_wait()
     {
         const int s = sense.load(std::memory_order_relaxed);
         if (count.fetch_sub(1, std::memory_order_acq_rel) == 1) {
-            count.store(64, std::memory_order_relaxed);
+            count.store(n, std::memory_order_relaxed);
             sense.store(s ^ 1, std::memory_order_release);
         } else {
             while (sense.load(std::memory_order_acquire) == s)
@@ -51,22 +59,42 @@ struct LaneBarrier {
     }
 };
 
+// gbar: one barrier per lane group, for kernels whose lane groups run
+// divergent code (set_groups); a lane whose t_group is below 64 meets only the
+// lanes of its group at a cross-lane operation.
 struct Wave {
     LaneBarrier bar;
-    uint64_t ex[64];
+    LaneBarrier gbar[32];
+    std::atomic<uint64_t> ex[64];
+    void set_groups(int g)
+    {
+        for (auto &b : gbar)
+            b.reset(g);
+    }
 };
 
 inline thread_local Wave *t_wave;
+inline thread_local int t_group = 64;          // lanes in the current scope
+inline thread_local void (*t_op_hook)(bool dpp) = nullptr;   // before each cross-lane op
 
 inline int lane_id() { return (int)(threadIdx.x & 63u); }
 
-inline uint64_t exchange(uint64_t x, int src, bool has_src, uint64_t old)
+inline LaneBarrier &scope_barrier(bool dpp)
+{
+    if (t_op_hook)
+        t_op_hook(dpp);
+    Wave &w = *t_wave;
+    return t_group >= 64 ? w.bar : w.gbar[lane_id() / t_group];
+}
+
+inline uint64_t exchange(uint64_t x, int src, bool has_src, uint64_t old, bool dpp = false)
 {
     Wave &w = *t_wave;
-    w.ex[lane_id()] = x;
-    w.bar.arrive_and_wait();
-    const uint64_t r = has_src ? w.ex[src & 63] : old;
-    w.bar.arrive_and_wait();
+    LaneBarrier &b = scope_barrier(dpp);
+    w.ex[lane_id()].store(x);
+    b.arrive_and_wait();
+    const uint64_t r = has_src ? w.ex[src & 63].load() : old;
+    b.arrive_and_wait();
     return r;
 }
 
@@ -103,10 +131,13 @@ struct Guarded {
     template <class T> T *as() { return static_cast<T *>(data); }
 };
 
-// Run fn on `waves` waves of one block (wave index = threadIdx.x >> 6).
-template <class F> void run_waves(int waves, F fn)
+// Run fn on `waves` waves of one block (wave index = threadIdx.x >> 6); `group`:
+// lanes per group for the barriers of a group's scope.
+template <class F> void run_waves(int waves, F fn, int group = 64)
 {
     std::vector<Wave> wv(waves);
+    for (auto &w : wv)
+        w.set_groups(group);
     std::vector<std::thread> th;
     for (int w = 0; w < waves; ++w)
         for (int l = 0; l < 64; ++l)
@@ -129,9 +160,9 @@ int model_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bo
         abort();
     const int l = lane_id();
     if (ctrl == 0x111)
-        return (int)exchange((uint32_t)src, l - 1, (l & 15) != 0, (uint32_t)old);
+        return (int)exchange((uint32_t)src, l - 1, (l & 15) != 0, (uint32_t)old, true);
     if (ctrl == 0x138)
-        return (int)exchange((uint32_t)src, l - 1, l != 0, (uint32_t)old);
+        return (int)exchange((uint32_t)src, l - 1, l != 0, (uint32_t)old, true);
     abort();
 }
 
@@ -153,14 +184,18 @@ int __shfl_up(int v, unsigned delta, int width)
 uint64_t __ballot(int pred)
 {
     // every lane's bit through the exchange slots, OR-ed by each lane
+    // (in a group's scope only the group's bits are gathered, the others are 0)
     using namespace wave_model;
     Wave &w = *t_wave;
-    w.ex[lane_id()] = pred ? 1u : 0u;
-    w.bar.arrive_and_wait();
+    LaneBarrier &b = scope_barrier(false);
+    const int g0 = t_group >= 64 ? 0 : lane_id() / t_group * t_group;
+    const int g1 = t_group >= 64 ? 64 : g0 + t_group;
+    w.ex[lane_id()].store(pred ? 1u : 0u);
+    b.arrive_and_wait();
     uint64_t r = 0;
-    for (int l = 0; l < 64; ++l)
-        r |= (w.ex[l] ? 1ull : 0ull) << l;
-    w.bar.arrive_and_wait();
+    for (int l = g0; l < g1; ++l)
+        r |= (w.ex[l].load() ? 1ull : 0ull) << l;
+    b.arrive_and_wait();
     return r;
 }
 uint32_t atomicAdd(uint32_t *p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }

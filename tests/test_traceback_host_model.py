@@ -3,16 +3,16 @@
 tests/host_model/traceback_model.cpp compiles the unmodified kernel file
 (paper_1304_0681_amd/csrc/traceback.hip) as C++ for the host, against the
 stand-in HIP header, on the lockstep wave model (lanes as threads meeting at a
-barrier around every cross-lane operation; DPP shifts, v_bitop3_b32,
-v_alignbit_b32 and v_bfe_i32 emulated from their definitions).  It runs the
-whole-wave tiles (64 lanes per pair: 8, 12 and 16 rows per lane for queries of
-257-1,024 bases, and the strip-mined tile above that), whose cross-lane
-operations are all wave-uniform, on pairs of lengths spread over each class,
-both strands, windows at and past the reference ends, with and without the
-band of the score pass's hits, and with selected ids that name no pair placed
-first.  Every array and the code scratch lie against a guard page (after their
-end, then before their start); coordinates, scores and CIGARs must equal the
-oracle's, and nothing outside the class may be written."""
+barrier around every cross-lane operation: the whole wave during the DP, only
+the lane group during the group's walk; DPP shifts, v_bitop3_b32,
+v_alignbit_b32 and v_bfe_i32 emulated from their definitions).  Every tile the
+library launches runs on pairs of lengths spread over its class, both strands,
+windows at and past the reference ends, with and without the band of the score
+pass's hits, with a last wave whose lane groups are partly idle, and with
+selected ids that name no pair placed first.  Every array and the code scratch
+lie against a guard page (after their end, then before their start);
+coordinates, scores and CIGARs must equal the oracle's, and nothing outside the
+class may be written."""
 import ctypes
 import os
 import subprocess
@@ -57,8 +57,9 @@ def _batch(seed, ms, ns, ref_len=40_000):
         seg = ref[b0:b0 + m].copy()
         mut = g.random(m) < 0.03
         seg[mut] = (seg[mut] + 1) % 4
-        k0 = int(g.integers(20, m - 20))
-        seg = np.concatenate([seg[:k0], seg[k0 + 3:], g.integers(0, 4, 3).astype(np.uint8)])
+        if m > 45:      # a 3-base deletion
+            k0 = int(g.integers(20, m - 20))
+            seg = np.concatenate([seg[:k0], seg[k0 + 3:], g.integers(0, 4, 3).astype(np.uint8)])
         reads.append(synth.ASCII[(3 - seg[::-1]) if st else seg].tobytes())
         wins.append((len(reads) - 1, max(b0 - int(g.integers(0, max(1, n // 3))), 0), n, st))
     wins.append((0, 0, 300, 0))                       # at the reference start
@@ -66,8 +67,7 @@ def _batch(seed, ms, ns, ref_len=40_000):
     return synth.custom(synth.ASCII[ref].tobytes(), reads, wins)
 
 
-def _run(model, b, sel, ids, RPL, strip, at_end, hits, waves=2):
-    G = 64
+def _run(model, b, sel, ids, G, RPL, strip, at_end, hits, waves=2):
     m = b.read_len[b.windows["read_id"][sel[ids]]].astype(np.int64)
     n = np.minimum(b.windows["len"][sel[ids]].astype(np.int64),
                    len(b.ref) - b.windows["ref_begin"][sel[ids]].astype(np.int64))
@@ -85,24 +85,32 @@ def _run(model, b, sel, ids, RPL, strip, at_end, hits, waves=2):
     p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     sc = np.array(SC, np.int32)
     h = None if hits is None else np.ascontiguousarray(hits)
-    rc = model.model_traceback(RPL, int(strip), waves, int(at_end), p(ref2b), ctypes.c_uint64(len(b.ref)),
+    rc = model.model_traceback(G, RPL, int(strip), waves, int(at_end), p(ref2b), ctypes.c_uint64(len(b.ref)),
                                p(reads2b), ctypes.c_uint64(len(reads2b)),
                                p(np.ascontiguousarray(b.read_off, np.uint64)),
                                p(np.ascontiguousarray(b.read_len, np.uint16)),
                                ctypes.c_uint32(b.n_reads), p(win), ctypes.c_uint32(b.n_pairs),
                                p(sel), ctypes.c_uint32(len(sel)), p(ids), ctypes.c_uint32(len(ids)),
                                ctypes.c_uint32(nmax), ctypes.c_uint32(mmax), p(sc),
-                               None if h is None else p(h), ctypes.c_uint64(waves * slot),
+                               None if h is None else p(h), ctypes.c_uint64(waves * (64 // G) * slot),
                                p(aln), p(ops), ctypes.c_uint32(stride))
     assert rc == 0
     return aln, ops
 
 
-@pytest.mark.parametrize("RPL,strip,lo,hi", [(8, False, 256, 512), (12, False, 512, 768),
-                                             (16, False, 768, 1024), (32, True, 1024, 2400)])
-def test_whole_wave_traceback_on_host_equals_oracle(model, RPL, strip, lo, hi):
-    ms = sorted({lo + 1, lo + 2, (lo + hi) // 2, hi - 1, hi} - {2400}) + ([2300] if strip else [])
-    b = _batch(500 + RPL, ms, [hi // 2, 40, hi + 200, 1000])
+# (G, RPL, strip, class bounds lo < m <= hi): the library's traceback classes
+SHAPES = [(2, 8, False, 0, 16), (4, 8, False, 16, 32), (8, 8, False, 32, 64),
+          (8, 13, False, 64, 100), (16, 8, False, 100, 128), (8, 20, False, 128, 160),
+          (32, 8, False, 160, 256), (64, 8, False, 256, 512), (64, 12, False, 512, 768),
+          (64, 16, False, 768, 1024), (64, 32, True, 1024, 2400)]
+
+
+@pytest.mark.parametrize("G,RPL,strip,lo,hi", SHAPES)
+def test_traceback_on_host_equals_oracle(model, G, RPL, strip, lo, hi):
+    ppw = 64 // G
+    n_pairs = max(ppw + ppw // 2 + 1, 6)      # the last wave's groups partly idle
+    ms = [int(x) for x in np.linspace(lo + 1, min(hi, 2300), n_pairs).round()]
+    b = _batch(500 + 7 * G + RPL, ms, [max(hi // 2, 8), 40, hi + 200, 1000])
     pairs = np.arange(b.n_pairs, dtype=np.uint32)
     m = b.read_len[b.windows["read_id"]].astype(np.int64)
     cls = pairs[(m > lo) & (m <= hi)]
@@ -115,12 +123,12 @@ def test_whole_wave_traceback_on_host_equals_oracle(model, RPL, strip, lo, hi):
     for f in ("score", "read_end", "ref_end"):
         hits[f] = hits_all[f]
     for band, at_end in ((False, True), (True, False)):
-        aln, ops = _run(model, b, sel, ids, RPL, strip, at_end, hits if band else None)
+        aln, ops = _run(model, b, sel, ids, G, RPL, strip, at_end, hits if band else None)
         got = aln[ids]
         for f in ("score", "read_begin", "read_end", "ref_begin", "ref_end", "n_ops", "status"):
-            assert (got[f] == ra[f]).all(), (RPL, band, f, got[f], ra[f])
+            assert (got[f] == ra[f]).all(), (G, RPL, band, f, got[f], ra[f])
         for k, i in enumerate(ids):
             nn = int(ra[k]["n_ops"])
-            assert (ops[i, :nn] == rops[k, :nn]).all(), (RPL, band, k)
+            assert (ops[i, :nn] == rops[k, :nn]).all(), (G, RPL, band, k)
         others = np.setdiff1d(np.arange(len(sel)), ids)
         assert (aln["score"][others] == -7).all() and (ops[others] == 7).all()
