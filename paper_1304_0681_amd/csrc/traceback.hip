@@ -130,14 +130,14 @@ __device__ __forceinline__ uint32_t tb_window_word(const TBParams &P, int64_t rb
 
 // STRIP: queries longer than one strip of G*RPL rows (G == 64); the boundary
 // row between strips goes through the tail of the pair's slot.
-// Waves per SIMD: the 12-row tile is held to 128 VGPRs for four (a few
-// registers spill outside the cell loop; measured faster than three), the 13-,
-// 16- and 20-row tiles to 168 for three, the 32-row strip tile to 256 for two;
-// the 8-row tiles fit four as they are.
+// Waves per SIMD: the 12- and 13-row tiles are held to 128 VGPRs for four (a few
+// registers spill outside the cell loop; measured faster than three), the 16-
+// and 20-row tiles to 168 for three, the 32-row strip tile to 256 for two; the
+// 8-row tiles fit four as they are.
 template <int RPL>
 constexpr int tb_min_waves()
 {
-    return RPL >= 24 ? 2 : RPL == 12 ? 4 : (RPL == 13 || RPL == 16 || RPL == 20) ? 3 : 1;
+    return RPL >= 24 ? 2 : (RPL == 12 || RPL == 13) ? 4 : (RPL == 16 || RPL == 20) ? 3 : 1;
 }
 
 template <int G, int RPL, bool STRIP>
