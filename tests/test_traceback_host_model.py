@@ -67,7 +67,7 @@ def _batch(seed, ms, ns, ref_len=40_000):
     return synth.custom(synth.ASCII[ref].tobytes(), reads, wins)
 
 
-def _run(model, b, sel, ids, G, RPL, strip, at_end, hits, waves=2):
+def _run(model, b, sel, ids, G, RPL, strip, at_end, hits, waves=2, codes_words=None):
     m = b.read_len[b.windows["read_id"][sel[ids]]].astype(np.int64)
     n = np.minimum(b.windows["len"][sel[ids]].astype(np.int64),
                    len(b.ref) - b.windows["ref_begin"][sel[ids]].astype(np.int64))
@@ -92,7 +92,7 @@ def _run(model, b, sel, ids, G, RPL, strip, at_end, hits, waves=2):
                                ctypes.c_uint32(b.n_reads), p(win), ctypes.c_uint32(b.n_pairs),
                                p(sel), ctypes.c_uint32(len(sel)), p(ids), ctypes.c_uint32(len(ids)),
                                ctypes.c_uint32(nmax), ctypes.c_uint32(mmax), p(sc),
-                               None if h is None else p(h), ctypes.c_uint64(waves * (64 // G) * slot),
+                               None if h is None else p(h), ctypes.c_uint64(waves * (64 // G) * slot if codes_words is None else codes_words),
                                p(aln), p(ops), ctypes.c_uint32(stride))
     assert rc == 0
     return aln, ops
@@ -132,3 +132,20 @@ def test_traceback_on_host_equals_oracle(model, G, RPL, strip, lo, hi):
             assert (ops[i, :nn] == rops[k, :nn]).all(), (G, RPL, band, k)
         others = np.setdiff1d(np.arange(len(sel)), ids)
         assert (aln["score"][others] == -7).all() and (ops[others] == 7).all()
+
+
+@pytest.mark.parametrize("G,RPL,strip,lo,hi", [SHAPES[3], SHAPES[8]])
+def test_traceback_on_host_without_room_marks_pairs(model, G, RPL, strip, lo, hi):
+    """A code scratch too small for one wave's slots: every pair of the class is
+    marked (status 4, score -1, no ops) and nothing is read or written beyond
+    the scratch."""
+    ms = [int(x) for x in np.linspace(lo + 1, hi, 9).round()]
+    b = _batch(900 + G, ms, [200, 40, 1000])
+    m = b.read_len[b.windows["read_id"]].astype(np.int64)
+    cls = np.nonzero((m > lo) & (m <= hi))[0].astype(np.uint32)
+    sel = np.concatenate([[NONE], cls]).astype(np.uint32)
+    ids = np.arange(1, 1 + len(cls), dtype=np.uint32)
+    aln, ops = _run(model, b, sel, ids, G, RPL, strip, True, None, codes_words=16)
+    got = aln[ids]
+    assert (got["status"] == 4).all() and (got["score"] == -1).all() and (got["n_ops"] == 0).all()
+    assert aln["score"][0] == -7 and (ops == 7).all()
